@@ -1,0 +1,229 @@
+/*
+ * mas_pcg.h -- C ABI of the MI355X MAS-preconditioned PCG library
+ * (libmaspcg.so).
+ *
+ * The library solves the SPD Newton system  H dx = -grad E  of an IPC
+ * time step (StiffGIPC, arXiv 2411.06224, Sec. 3.2 "IP Minimization and
+ * Linear Solves": P(u) d = -grad E(u) with P symmetric positive definite) by
+ * preconditioned conjugate gradients, preconditioned with the
+ * connectivity-enhanced multilevel additive Schwarz (MAS) operator
+ *
+ *     M^-1 = sum_l C_l^T blockdiag_d( (S_d C_l H C_l^T S_d^T)^-1 ) C_l
+ *
+ * (Supp. Eq. 4-6; domains from a connectivity-aware partition with padding,
+ * Sec. 3.2 and Fig. mapping; coarse levels from connected components inside
+ * each domain, Sec. 3.1 and Supp. Alg. 2-5; per-domain matrices from the
+ * algorithm "Compute MAS preconditioner" and inverted over unpadded lanes).
+ *
+ * Conventions
+ *  - H is 3x3-block CSR (the block rows/columns of the paper's matrix AG):
+ *    row_ptr[n_rows+1] and col_idx[nnzb] are int32 with columns ascending in
+ *    each row; val holds nnzb row-major 3x3 blocks (9 values each).  Both
+ *    triangles are stored, every row holds its diagonal block, and H must be
+ *    symmetric (val(j,i) = val(i,j)^T).  One block row per mesh node.
+ *  - Vectors are 3*n_rows doubles, node-major (x[3*i + c]).
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary CPU memory.  The library never frees or keeps
+ *    ownership of caller memory.  All device memory the library needs comes
+ *    from the caller's workspace (see mas_workspace_size); the library itself
+ *    allocates only small pinned host buffers inside the handle.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on that stream; calls that report results (mas_build,
+ *    pcg_solve, pcg_adjoint) synchronise it before returning.
+ *  - Every call returns a mas_status; no call throws or aborts.
+ *  - Thread safety: a handle may be used by one stream at a time.
+ */
+#ifndef MAS_PCG_H
+#define MAS_PCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+typedef enum {
+    MAS_OK = 0,
+    MAS_NOT_CONVERGED = 1,       /* max_iter reached; outputs hold the last iterate */
+    MAS_INVALID_ARG = -1,        /* bad size, pointer, option or pattern */
+    MAS_NOT_SPD = -2,            /* a domain pivot <= 0, or p^T H p <= 0 in PCG */
+    MAS_HIP_ERROR = -3,          /* a HIP runtime call failed */
+    MAS_WORKSPACE_TOO_SMALL = -4,/* ws_bytes < mas_workspace_size() */
+    MAS_NOT_READY = -5,          /* call order: analyze -> build -> apply/solve */
+    MAS_NOT_FINITE = -6          /* NaN/Inf met in a residual norm */
+} mas_status;
+
+/* Value types of a BCSR matrix. */
+enum { MAS_F64 = 0, MAS_F32 = 1 };
+
+/* Solver precision modes. */
+enum {
+    MAS_PRECISION_F64 = 0,   /* everything FP64 */
+    MAS_PRECISION_MIXED = 1  /* H values and domain inverses stored and applied in FP32;
+                                domain inversion, dot products, alpha/beta and the x/r
+                                updates in FP64; FP64 residual replacement */
+};
+
+#define MAS_MAX_LEVELS 16
+#define MAS_MAX_DOMAIN_SIZE 40
+
+/* A 3x3-block CSR matrix in device memory (layout above). */
+typedef struct {
+    int32_t n_rows;          /* number of block rows (nodes) */
+    int32_t nnzb;            /* number of stored 3x3 blocks */
+    const int32_t* row_ptr;  /* device, n_rows + 1 */
+    const int32_t* col_idx;  /* device, nnzb */
+    const void* val;         /* device, nnzb * 9 values of type dtype */
+    int32_t dtype;           /* MAS_F64 or MAS_F32 */
+} mas_bcsr;
+
+typedef struct {
+    int32_t domain_size;     /* N: nodes per level-0 domain, 1..MAS_MAX_DOMAIN_SIZE (paper: 16) */
+    int32_t max_levels;      /* <= 0: build levels until one domain or no merge */
+    int32_t precision;       /* MAS_PRECISION_F64 or MAS_PRECISION_MIXED */
+    int32_t reserved;        /* must be 0 */
+} mas_options;
+
+typedef struct {
+    double tol;              /* stop when ||r||_2 <= tol * ||b||_2 */
+    int32_t max_iter;        /* >= 0 */
+    int32_t x0_given;        /* 1: x holds the initial guess, else x0 = 0 */
+    int32_t replace_every;   /* mixed mode: FP64 residual replacement period (0 -> 50) */
+    int32_t check_every;     /* iterations between host convergence checks (0 -> 8) */
+} pcg_options;
+
+typedef struct {
+    int32_t status;          /* same as the return value */
+    int32_t iterations;      /* CG iterations performed */
+    double rel_residual;     /* ||r||/||b|| of the recurrence at exit */
+    double true_rel_residual;/* ||b - H x||/||b|| recomputed with FP64 H */
+} pcg_result;
+
+/* Static description of an analysed handle (host copy). */
+typedef struct {
+    int32_t n_rows, nnzb, domain_size, parts, slack, levels;
+    int32_t units[MAS_MAX_LEVELS];    /* level 0: parts*domain_size slots; l >= 1: supernodes */
+    int32_t domains[MAS_MAX_LEVELS];  /* domains per level */
+    int32_t coarse_nnzb[MAS_MAX_LEVELS]; /* stored blocks of the level-l coarse matrix (l >= 1) */
+    int64_t workspace_bytes;
+    int64_t inverse_bytes;            /* bytes of domain inverses (all levels, as stored) */
+} mas_info;
+
+typedef struct mas_handle mas_handle;
+
+/* Creates an empty handle.  opts may be NULL (N = 16, all levels, FP64).
+ * Errors: MAS_INVALID_ARG for out-of-range options. */
+int mas_create(const mas_options* opts, mas_handle** out);
+
+/* Frees the handle and its pinned host buffers (never the workspace). */
+void mas_destroy(mas_handle* h);
+
+/* Symbolic phase, on the host, once per sparsity pattern (the paper runs its
+ * METIS reordering once at load, Sec. 3.2): partition of the node graph into
+ * M = ceil(V/(N - N_o)) parts of at most N nodes with the smallest slack N_o
+ * (Eq. num_subdomains), map/remap with -1 padding, supernode hierarchy from
+ * the block pattern of H (contact couplings included), and every gather /
+ * reduction plan the device phases use.
+ *   row_ptr, col_idx: host copies of H's pattern (conventions above).
+ *   g_ptr, g_adj: host CSR node graph to partition (e.g. mesh edges); both
+ *                 NULL = the off-diagonal pattern of H.  Self loops and
+ *                 duplicates are ignored; the graph is symmetrised.
+ * Errors: MAS_INVALID_ARG (sizes, unsorted or out-of-range columns, missing
+ * diagonal block, asymmetric pattern). */
+int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                const int32_t* g_ptr, const int32_t* g_adj);
+
+/* Device bytes the handle needs (valid after mas_analyze; 0 before). */
+size_t mas_workspace_size(const mas_handle* h);
+
+/* Numeric phase on the device (algorithm "Compute MAS preconditioner"):
+ * sums the coarse matrices C_l H C_l^T level by level, gathers every domain
+ * matrix S_d C_l H C_l^T S_d^T and inverts it over its occupied lanes in FP64
+ * (batched, LDS-resident, MFMA tiles); in mixed mode also stores FP32 copies
+ * of the inverses.
+ *   H: device matrix with the analysed pattern, dtype MAS_F64.
+ *   workspace: device buffer of ws_bytes >= mas_workspace_size(h), 256-byte
+ *              aligned, owned by the caller and kept alive while the handle
+ *              is used; it holds plans, values, inverses and solver vectors.
+ * Synchronises the stream.  Errors: MAS_NOT_READY (no analyze),
+ * MAS_WORKSPACE_TOO_SMALL, MAS_INVALID_ARG, MAS_NOT_SPD (a domain matrix is
+ * not positive definite), MAS_HIP_ERROR. */
+int mas_build(mas_handle* h, const mas_bcsr* H, void* workspace, size_t ws_bytes, void* stream);
+
+/* z = M^-1 r (Supp. Eq. 6): restrict r to every level, multiply each domain
+ * by its inverse, prolong and sum over levels.  r, z: device, 3*n_rows
+ * doubles, node order; may not alias.  Uses the precision chosen at create.
+ * Asynchronous.  Errors: MAS_NOT_READY, MAS_INVALID_ARG, MAS_HIP_ERROR. */
+int mas_apply(mas_handle* h, const double* r, double* z, void* stream);
+
+/* y = H x for a 3x3-block CSR matrix (FP64 or FP32 values, FP64 vectors).
+ * x, y: device, 3*n_rows doubles; may not alias.  Needs no handle.
+ * Asynchronous.  Errors: MAS_INVALID_ARG, MAS_HIP_ERROR. */
+int bcsr_spmv(const mas_bcsr* H, const double* x, double* y, void* stream);
+
+/* Solves H x = b by PCG with the handle's MAS preconditioner.
+ *   H: device, FP64, the analysed pattern.  Its current values are permuted
+ *      into domain order (plus an FP32 copy in mixed mode) at the start of
+ *      every call; the preconditioner is the one built by the last mas_build.
+ *   b, x: device, 3*n_rows doubles (x may hold x0 when opts->x0_given).
+ *   opts: NULL = tol 1e-4, max_iter 10000.  res: host, may be NULL.
+ * Stops when ||r||_2 <= tol ||b||_2; in mixed mode the stop is confirmed on
+ * the FP64 residual b - H x.  b = 0 gives x = 0 after 0 iterations.
+ * Synchronises the stream.  Returns MAS_OK, MAS_NOT_CONVERGED (x holds the
+ * last iterate), MAS_NOT_SPD, MAS_NOT_FINITE, MAS_INVALID_ARG, MAS_NOT_READY
+ * or MAS_HIP_ERROR. */
+int pcg_solve(mas_handle* h, const mas_bcsr* H, const double* b, double* x, const pcg_options* opts,
+              pcg_result* res, void* stream);
+
+/* Backward of x = H^-1 b for a loss L(x): solves H lambda = dL/dx with the
+ * same MAS (H is symmetric, so the forward preconditioner serves the adjoint
+ * system), then writes dL/db = lambda and dL/dH_ij = -lambda_i x_j^T on every
+ * stored block (from dx = -H^-1 dH x).
+ *   x: device, the forward solution; dLdx: device, 3*n_rows doubles.
+ *   lambda: device, 3*n_rows doubles (= dL/db).
+ *   dLdH: device, nnzb*9 values of type dLdH_dtype (MAS_F64 or MAS_F32), in
+ *         H's block order, row-major 3x3; NULL skips the scatter.
+ * Synchronises the stream.  Errors as pcg_solve. */
+int pcg_adjoint(mas_handle* h, const mas_bcsr* H, const double* x, const double* dLdx, double* lambda, void* dLdH,
+                int32_t dLdH_dtype, const pcg_options* opts, pcg_result* res, void* stream);
+
+/* Host copy of the handle's static description (after mas_analyze). */
+int mas_get_info(const mas_handle* h, mas_info* out);
+
+/* Host copies of the ordering: map[n_rows] (node -> level-0 slot),
+ * remap[parts*domain_size] (slot -> node or -1), sn[levels*n_rows]
+ * (unit of each node at each level; level 0 = slot).  Any pointer may be
+ * NULL.  Errors: MAS_NOT_READY. */
+int mas_get_ordering(const mas_handle* h, int32_t* map, int32_t* remap, int32_t* sn);
+
+/* Device time in milliseconds of the phases of the last mas_build and
+ * pcg_solve / pcg_adjoint call on this handle, measured with HIP events on
+ * the call's stream: [0] coarse sums and [1] batched inversion (mas_build),
+ * [2] permutation of H into domain order and [3] the PCG iterations with
+ * their setup and final residual check (pcg_solve). */
+int mas_get_timings(const mas_handle* h, double* ms4);
+
+/* Per-launch kernel timing for measurement.  With enable != 0 every later
+ * pcg_solve / pcg_adjoint brackets each launch of its iteration kernels with
+ * a pair of HIP events on the call's stream and accumulates the elapsed
+ * times (this adds event packets between launches, so leave it off for
+ * timed runs).  Enabling or disabling clears the totals. */
+int mas_set_kernel_timing(mas_handle* h, int enable);
+
+/* Totals since the last mas_set_kernel_timing: total_ms[8] and launches[8]
+ * for the kernel slots [0] SpMV q = H p with p^T q, [1] x/r update with
+ * ||r||^2 and restriction to level 1, [2] coarse-level MAS apply,
+ * [3] level-0 MAS apply with prolongation and r^T z, [4] p = z + beta p,
+ * [5] FP64 residual replacement, [6] permutation of H, [7] restriction
+ * only.  Host arrays. */
+int mas_get_kernel_timing(const mas_handle* h, double* total_ms, int32_t* launches);
+
+/* Short English description of a status code (static string). */
+const char* mas_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

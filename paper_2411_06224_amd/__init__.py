@@ -1,0 +1,22 @@
+"""MI355X-native MAS-preconditioned PCG (StiffGIPC, arXiv 2411.06224).
+
+The solver is the C-ABI library ``libmaspcg.so`` (HIP kernels for gfx950 and
+a C++ host planner, see include/mas_pcg.h); this package only marshals
+arguments.  Importing it does not load the library; the first call does, and
+fails loudly if the library has not been built.
+"""
+
+from ._lib import LibraryMissing, MasError, load
+from .solver import BlockMatrix, MasPcg, bcsr_spmv
+from .autograd import MasPcgSolve, mas_pcg_solve
+
+__all__ = [
+    "BlockMatrix",
+    "MasPcg",
+    "bcsr_spmv",
+    "MasPcgSolve",
+    "mas_pcg_solve",
+    "LibraryMissing",
+    "MasError",
+    "load",
+]

@@ -1,0 +1,611 @@
+// C ABI of libmaspcg (declared in include/mas_pcg.h): handle, workspace
+// layout and the host-side driver of the PCG iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mas_pcg.h"
+#include "launch.hpp"
+#include "planner.hpp"
+
+using namespace maspcg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Layout {
+    size_t total = 0;
+    size_t remap, map, perm_src, rp0, ci0, lead1, anc;
+    size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
+    size_t mem_ptr[kMaxLv], mem_idx[kMaxLv];
+    size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
+    size_t b, x, r, z, p, q, r1, y[kMaxLv], partials, st, flag;
+    size_t inverse_bytes = 0;
+
+    size_t take(size_t bytes) {
+        const size_t o = (total + kAlign - 1) / kAlign * kAlign;
+        total = o + std::max<size_t>(bytes, 1);
+        return o;
+    }
+};
+
+enum { kEvBuild0 = 0, kEvBuild1, kEvBuild2, kEvSolve0, kEvSolve1, kEvSolve2, kEvCount };
+
+// Kernel slots of the optional per-launch timing (mas_set_kernel_timing).
+enum { kKSpmv = 0, kKUpdate, kKCoarse, kKLevel0, kKUpdateP, kKResidual, kKPermute, kKRestrict, kKSlots };
+
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> pending;  // kernel slot of each started pair
+    double total_ms[kKSlots] = {0};
+    int launches[kKSlots] = {0};
+};
+
+}  // namespace
+
+struct mas_handle {
+    mas_options opts{};
+    bool analyzed = false;
+    Plan plan;
+    Layout lay;
+    std::vector<std::vector<int>> translated;  // level-1 reduction sources and level-0 domain blocks in caller order
+    char* ws = nullptr;
+    size_t ws_size = 0;
+    char* uploaded_to = nullptr;
+    bool built = false;
+    DevState* st_host = nullptr;  // pinned
+    int* flag_host = nullptr;     // pinned
+    hipEvent_t ev[kEvCount]{};
+    bool events = false;
+    double timings[4] = {0, 0, 0, 0};
+    KernelTimer kt;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                \
+    do {                                             \
+        if ((expr) != hipSuccess) return MAS_HIP_ERROR; \
+    } while (0)
+
+// Runs one launch; with kernel timing on, brackets it with a pair of HIP
+// events on the same stream (resolved at the next synchronisation).
+template <typename F>
+hipError_t timed(mas_handle* h, int slot, hipStream_t s, F&& launch) {
+    KernelTimer& t = h->kt;
+    if (!t.on) return launch();
+    if (t.used + 2 > t.pool.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) return err;
+            t.pool.push_back(e);
+        }
+    }
+    hipError_t err = hipEventRecord(t.pool[t.used], s);
+    if (err != hipSuccess) return err;
+    err = launch();
+    if (err != hipSuccess) return err;
+    err = hipEventRecord(t.pool[t.used + 1], s);
+    if (err != hipSuccess) return err;
+    t.used += 2;
+    t.pending.push_back(slot);
+    return hipSuccess;
+}
+
+// Called after the stream has been synchronised.
+void collect_timing(mas_handle* h) {
+    KernelTimer& t = h->kt;
+    for (size_t k = 0; k < t.pending.size(); ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.pool[2 * k], t.pool[2 * k + 1]) == hipSuccess) {
+            t.total_ms[t.pending[k]] += ms;
+            t.launches[t.pending[k]] += 1;
+        }
+    }
+    t.pending.clear();
+    t.used = 0;
+}
+
+template <typename T>
+T* at(const mas_handle* h, size_t off) {
+    return reinterpret_cast<T*>(h->ws + off);
+}
+
+void make_layout(mas_handle* h) {
+    const Plan& P = h->plan;
+    Layout& Y = h->lay;
+    Y = Layout();
+    const bool mixed = h->opts.precision == MAS_PRECISION_MIXED;
+    const size_t I = sizeof(int), Dd = sizeof(double), F = sizeof(float);
+    const int n = 3 * P.N;
+    Y.remap = Y.take(I * P.NS);
+    Y.map = Y.take(I * P.V);
+    Y.perm_src = Y.take(I * P.nnzb);
+    Y.rp0 = Y.take(I * (P.NS + 1));
+    Y.ci0 = Y.take(I * P.nnzb);
+    Y.lead1 = Y.take(I * P.NS);
+    Y.anc = Y.take(I * P.anc.size());
+    for (int l = 0; l < P.L; ++l) {
+        if (l >= 1) {
+            Y.red_ptr[l] = Y.take(I * P.red_ptr[l].size());
+            Y.red_src[l] = Y.take(I * P.red_src[l].size());
+        }
+        Y.dom_ptr[l] = Y.take(I * P.dom_ptr[l].size());
+        Y.dom_blk[l] = Y.take(I * P.dom_blk[l].size());
+        Y.dom_ab[l] = Y.take(I * P.dom_ab[l].size());
+        if (l >= 2) {
+            Y.mem_ptr[l] = Y.take(I * P.mem_ptr[l].size());
+            Y.mem_idx[l] = Y.take(I * P.mem_idx[l].size());
+        }
+    }
+    Y.H64 = Y.take(Dd * 9 * P.nnzb);
+    Y.H32 = mixed ? Y.take(F * 9 * P.nnzb) : 0;
+    for (int l = 1; l < P.L; ++l) Y.A[l] = Y.take(Dd * 9 * P.ciA[l].size());
+    for (int l = 0; l < P.L; ++l) {
+        const size_t cnt = static_cast<size_t>(P.ndom[l]) * n * n;
+        Y.inv64[l] = Y.take(Dd * cnt);
+        Y.inverse_bytes += (mixed ? F : Dd) * cnt;
+        if (mixed) Y.inv32[l] = Y.take(F * cnt);
+    }
+    const size_t vec = Dd * 3 * P.NS;
+    Y.b = Y.take(vec);
+    Y.x = Y.take(vec);
+    Y.r = Y.take(vec);
+    Y.z = Y.take(vec);
+    Y.p = Y.take(vec);
+    Y.q = Y.take(vec);
+    Y.r1 = Y.take(Dd * 3 * (P.L > 1 ? P.units[1] : 1));
+    for (int l = 1; l < P.L; ++l) Y.y[l] = Y.take(Dd * 3 * static_cast<size_t>(P.ndom[l]) * P.N);
+    const int g = std::max({grid_spmv_rows(P.NS), grid_update(P.M, P.N), grid_apply0(P.M, P.N), 1024});
+    Y.partials = Y.take(Dd * 2 * g);
+    Y.st = Y.take(sizeof(DevState));
+    Y.flag = Y.take(I);
+}
+
+SolverView view(const mas_handle* h) {
+    const Plan& P = h->plan;
+    const Layout& Y = h->lay;
+    SolverView v{};
+    v.V = P.V;
+    v.N = P.N;
+    v.M = P.M;
+    v.NS = P.NS;
+    v.L = P.L;
+    v.nnzb = P.nnzb;
+    for (int l = 0; l < P.L; ++l) {
+        v.units[l] = P.units[l];
+        v.ndom[l] = P.ndom[l];
+        v.inv64[l] = at<double>(h, Y.inv64[l]);
+        v.inv32[l] = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.inv32[l]) : nullptr;
+        if (l >= 2) {
+            v.mem_ptr[l] = at<int>(h, Y.mem_ptr[l]);
+            v.mem_idx[l] = at<int>(h, Y.mem_idx[l]);
+        }
+        if (l >= 1) v.y[l] = at<double>(h, Y.y[l]);
+    }
+    v.remap = at<int>(h, Y.remap);
+    v.map = at<int>(h, Y.map);
+    v.perm_src = at<int>(h, Y.perm_src);
+    v.rp0 = at<int>(h, Y.rp0);
+    v.ci0 = at<int>(h, Y.ci0);
+    v.lead1 = at<int>(h, Y.lead1);
+    v.anc = at<int>(h, Y.anc);
+    v.H64 = at<double>(h, Y.H64);
+    v.H32 = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.H32) : nullptr;
+    v.b = at<double>(h, Y.b);
+    v.x = at<double>(h, Y.x);
+    v.r = at<double>(h, Y.r);
+    v.z = at<double>(h, Y.z);
+    v.p = at<double>(h, Y.p);
+    v.q = at<double>(h, Y.q);
+    v.r1 = at<double>(h, Y.r1);
+    v.partials = at<double>(h, Y.partials);
+    v.st = at<DevState>(h, Y.st);
+    v.flag = at<int>(h, Y.flag);
+    return v;
+}
+
+BuildView build_view(const mas_handle* h) {
+    const Plan& P = h->plan;
+    const Layout& Y = h->lay;
+    BuildView b{};
+    b.L = P.L;
+    b.N = P.N;
+    b.nnzb = P.nnzb;
+    for (int l = 0; l < P.L; ++l) {
+        b.units[l] = P.units[l];
+        b.ndom[l] = P.ndom[l];
+        b.nnzA[l] = l == 0 ? P.nnzb : static_cast<int>(P.ciA[l].size());
+        if (l >= 1) {
+            b.red_ptr[l] = at<int>(h, Y.red_ptr[l]);
+            b.red_src[l] = at<int>(h, Y.red_src[l]);
+            b.A[l] = at<double>(h, Y.A[l]);
+        }
+        b.dom_ptr[l] = at<int>(h, Y.dom_ptr[l]);
+        b.dom_blk[l] = at<int>(h, Y.dom_blk[l]);
+        b.dom_ab[l] = at<int>(h, Y.dom_ab[l]);
+        b.inv64[l] = at<double>(h, Y.inv64[l]);
+        b.inv32[l] = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.inv32[l]) : nullptr;
+    }
+    b.remap = at<int>(h, Y.remap);
+    b.flag = at<int>(h, Y.flag);
+    return b;
+}
+
+int upload_plan(mas_handle* h, hipStream_t s) {
+    const Plan& P = h->plan;
+    const Layout& Y = h->lay;
+    auto put = [&](size_t off, const std::vector<int>& v) -> hipError_t {
+        if (v.empty()) return hipSuccess;
+        return hipMemcpyAsync(h->ws + off, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    };
+    HIP_TRY(put(Y.remap, P.remap));
+    HIP_TRY(put(Y.map, P.map));
+    HIP_TRY(put(Y.perm_src, P.perm_src));
+    HIP_TRY(put(Y.rp0, P.rp0));
+    HIP_TRY(put(Y.ci0, P.ci0));
+    HIP_TRY(put(Y.lead1, P.lead1));
+    HIP_TRY(put(Y.anc, P.anc));
+    for (int l = 0; l < P.L; ++l) {
+        if (l >= 1) {
+            HIP_TRY(put(Y.red_ptr[l], P.red_ptr[l]));
+            HIP_TRY(put(Y.red_src[l], l == 1 ? h->translated[0] : P.red_src[l]));
+        }
+        HIP_TRY(put(Y.dom_ptr[l], P.dom_ptr[l]));
+        HIP_TRY(put(Y.dom_blk[l], l == 0 ? h->translated[1] : P.dom_blk[l]));
+        HIP_TRY(put(Y.dom_ab[l], P.dom_ab[l]));
+        if (l >= 2) {
+            HIP_TRY(put(Y.mem_ptr[l], P.mem_ptr[l]));
+            HIP_TRY(put(Y.mem_idx[l], P.mem_idx[l]));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s));  // the host vectors are pageable
+    return MAS_OK;
+}
+
+bool bcsr_ok(const mas_handle* h, const mas_bcsr* H) {
+    return H && H->row_ptr && H->col_idx && H->val && H->n_rows == h->plan.V && H->nnzb == h->plan.nnzb &&
+           H->dtype == MAS_F64;
+}
+
+int finish_status(const DevState& st) {
+    if (st.status == -2) return MAS_NOT_SPD;
+    if (st.status == -6) return MAS_NOT_FINITE;
+    if (st.done && st.status == 0) return MAS_OK;
+    return MAS_NOT_CONVERGED;
+}
+
+hipError_t restrict_r(mas_handle* h, const SolverView& v, bool mixed, hipStream_t s) {
+    if (v.L < 2) return hipSuccess;
+    return timed(h, kKRestrict, s, [&] { return launch_update(v, true, mixed, s); });
+}
+
+hipError_t apply_init(mas_handle* h, const SolverView& v, bool mixed, hipStream_t s) {
+    hipError_t e;
+    if ((e = restrict_r(h, v, mixed, s)) != hipSuccess) return e;
+    if ((e = launch_apply_coarse(v, mixed, kApplyInit, s)) != hipSuccess) return e;
+    return launch_apply_level0(v, mixed, kApplyInit, s);
+}
+
+hipError_t finish_iteration(mas_handle* h, const SolverView& v, bool mixed, hipStream_t s) {
+    hipError_t e;
+    if ((e = timed(h, kKCoarse, s, [&] { return launch_apply_coarse(v, mixed, kApplyIter, s); })) != hipSuccess) return e;
+    if ((e = timed(h, kKLevel0, s, [&] { return launch_apply_level0(v, mixed, kApplyIter, s); })) != hipSuccess)
+        return e;
+    return timed(h, kKUpdateP, s, [&] { return launch_update_p(v, false, s); });
+}
+
+int read_state(mas_handle* h, const SolverView& v, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(h->st_host, v.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    collect_timing(h);
+    return MAS_OK;
+}
+
+// The PCG driver shared by pcg_solve and pcg_adjoint.
+int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, const pcg_options* o, pcg_result* res,
+               hipStream_t s) {
+    if (!h || !h->analyzed) return MAS_NOT_READY;
+    if (!h->built) return MAS_NOT_READY;
+    if (!bcsr_ok(h, H) || !b || !x || b == x) return MAS_INVALID_ARG;
+    pcg_options opt{1e-4, 10000, 0, 50, 8};
+    if (o) opt = *o;
+    if (!(opt.tol >= 0.0) || opt.max_iter < 0) return MAS_INVALID_ARG;
+    if (opt.replace_every <= 0) opt.replace_every = 50;
+    if (opt.check_every <= 0) opt.check_every = 8;
+    const bool mixed = h->opts.precision == MAS_PRECISION_MIXED;
+    const SolverView v = view(h);
+
+    HIP_TRY(hipEventRecord(h->ev[kEvSolve0], s));
+    HIP_TRY(timed(h, kKPermute, s, [&] { return launch_permute_H(v, static_cast<const double*>(H->val), mixed, s); }));
+    HIP_TRY(hipEventRecord(h->ev[kEvSolve1], s));
+    HIP_TRY(launch_state_reset(v, s));
+    HIP_TRY(launch_perm_in(v, b, v.b, s));
+    if (opt.x0_given) {
+        HIP_TRY(launch_perm_in(v, x, v.x, s));
+        HIP_TRY(launch_residual(v, kResidInit, opt.tol, v.r, s));
+    } else {
+        HIP_TRY(launch_init_rhs(v, opt.tol, s));
+    }
+    HIP_TRY(apply_init(h, v, mixed, s));
+    HIP_TRY(launch_update_p(v, true, s));  // p = z
+
+    int enq = 0;
+    int rc = MAS_OK;
+    DevState& st = *h->st_host;
+    for (;;) {
+        const int nb = std::min(opt.check_every, opt.max_iter - enq);
+        for (int i = 0; i < nb; ++i) {
+            const int k = enq + i + 1;
+            HIP_TRY(timed(h, kKSpmv, s, [&] { return launch_spmv_pq(v, mixed, s); }));
+            HIP_TRY(timed(h, kKUpdate, s, [&] { return launch_update(v, false, mixed, s); }));
+            if (mixed && k % opt.replace_every == 0) {
+                HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidPeriodic, opt.tol, v.r, s); }));
+                HIP_TRY(restrict_r(h, v, mixed, s));
+            }
+            HIP_TRY(finish_iteration(h, v, mixed, s));
+        }
+        enq += nb;
+        if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
+        if (st.status < 0) break;
+        if (st.done) {
+            if (st.status != kStatusConvergedRecurrence) break;
+            // confirm on the FP64 residual b - H x (also a residual replacement)
+            HIP_TRY(launch_residual(v, kResidConfirm, opt.tol, v.r, s));
+            if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
+            if (st.done || st.status < 0) break;
+            enq = st.iter;
+            HIP_TRY(restrict_r(h, v, mixed, s));
+            HIP_TRY(finish_iteration(h, v, mixed, s));
+        }
+        if (enq >= opt.max_iter) break;
+    }
+    if (st.bb == 0.0)  // b = 0: the solution is x = b = 0 (also when an x0 was given)
+        HIP_TRY(hipMemcpyAsync(v.x, v.b, sizeof(double) * 3 * v.NS, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_residual(v, kResidFinal, opt.tol, v.q, s));
+    HIP_TRY(launch_perm_out(v, v.x, x, s));
+    HIP_TRY(hipEventRecord(h->ev[kEvSolve2], s));
+    if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
+
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[kEvSolve0], h->ev[kEvSolve1]) == hipSuccess) h->timings[2] = ms;
+    if (hipEventElapsedTime(&ms, h->ev[kEvSolve1], h->ev[kEvSolve2]) == hipSuccess) h->timings[3] = ms;
+
+    rc = finish_status(st);
+    if (st.bb == 0.0 && st.status == 0) rc = MAS_OK;
+    if (res) {
+        res->status = rc;
+        res->iterations = st.iter;
+        res->rel_residual = st.bb > 0 ? std::sqrt(st.rr / st.bb) : 0.0;
+        res->true_rel_residual = st.bb > 0 ? std::sqrt(st.rr_true / st.bb) : 0.0;
+    }
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mas_create(const mas_options* opts, mas_handle** out) {
+    if (!out) return MAS_INVALID_ARG;
+    *out = nullptr;
+    mas_options o{16, 0, MAS_PRECISION_F64, 0};
+    if (opts) o = *opts;
+    if (o.domain_size < 1 || o.domain_size > MAS_MAX_DOMAIN_SIZE) return MAS_INVALID_ARG;
+    if (o.precision != MAS_PRECISION_F64 && o.precision != MAS_PRECISION_MIXED) return MAS_INVALID_ARG;
+    if (o.reserved != 0 || o.max_levels > MAS_MAX_LEVELS) return MAS_INVALID_ARG;
+    mas_handle* h = new (std::nothrow) mas_handle();
+    if (!h) return MAS_HIP_ERROR;
+    h->opts = o;
+    *out = h;
+    return MAS_OK;
+}
+
+void mas_destroy(mas_handle* h) {
+    if (!h) return;
+    if (h->st_host) (void)hipHostFree(h->st_host);
+    if (h->flag_host) (void)hipHostFree(h->flag_host);
+    if (h->events)
+        for (auto& e : h->ev) (void)hipEventDestroy(e);
+    for (auto& e : h->kt.pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                const int32_t* g_ptr, const int32_t* g_adj) {
+    if (!h) return MAS_INVALID_ARG;
+    Plan P;
+    const std::string err = analyze(n_rows, nnzb, row_ptr, col_idx, g_ptr, g_adj, h->opts.domain_size,
+                                    h->opts.max_levels, P);
+    if (!err.empty()) return MAS_INVALID_ARG;
+    h->plan = std::move(P);
+    h->analyzed = true;
+    h->built = false;
+    h->uploaded_to = nullptr;
+    // level-1 reduction sources and level-0 inversion blocks in caller block order
+    h->translated.assign(2, {});
+    const Plan& Q = h->plan;
+    if (Q.L > 1) {
+        h->translated[0].resize(Q.red_src[1].size());
+        for (size_t k = 0; k < Q.red_src[1].size(); ++k) h->translated[0][k] = Q.perm_src[Q.red_src[1][k]];
+    }
+    h->translated[1].resize(Q.dom_blk[0].size());
+    for (size_t k = 0; k < Q.dom_blk[0].size(); ++k) h->translated[1][k] = Q.perm_src[Q.dom_blk[0][k]];
+    make_layout(h);
+    return MAS_OK;
+}
+
+size_t mas_workspace_size(const mas_handle* h) { return (h && h->analyzed) ? h->lay.total : 0; }
+
+int mas_build(mas_handle* h, const mas_bcsr* H, void* workspace, size_t ws_bytes, void* stream) {
+    if (!h) return MAS_INVALID_ARG;
+    if (!h->analyzed) return MAS_NOT_READY;
+    if (!bcsr_ok(h, H) || !workspace) return MAS_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < h->lay.total) return MAS_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!h->st_host) {
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->st_host), sizeof(DevState), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), sizeof(int), hipHostMallocDefault));
+    }
+    if (!h->events) {
+        for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
+        h->events = true;
+    }
+    h->ws = static_cast<char*>(workspace);
+    h->ws_size = ws_bytes;
+    h->built = false;
+    if (h->uploaded_to != h->ws) {
+        int rc = upload_plan(h, s);
+        if (rc != MAS_OK) return rc;
+        h->uploaded_to = h->ws;
+    }
+    const SolverView v = view(h);
+    const BuildView bv = build_view(h);
+    const bool mixed = h->opts.precision == MAS_PRECISION_MIXED;
+    const double* Hu = static_cast<const double*>(H->val);
+    *h->flag_host = 0;
+    HIP_TRY(hipMemcpyAsync(v.flag, h->flag_host, sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_state_reset(v, s));
+    HIP_TRY(hipEventRecord(h->ev[kEvBuild0], s));
+    HIP_TRY(launch_coarse_sums(bv, Hu, s));
+    HIP_TRY(hipEventRecord(h->ev[kEvBuild1], s));
+    HIP_TRY(launch_invert(bv, Hu, mixed, s));
+    HIP_TRY(hipEventRecord(h->ev[kEvBuild2], s));
+    HIP_TRY(hipMemcpyAsync(h->flag_host, v.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[kEvBuild0], h->ev[kEvBuild1]) == hipSuccess) h->timings[0] = ms;
+    if (hipEventElapsedTime(&ms, h->ev[kEvBuild1], h->ev[kEvBuild2]) == hipSuccess) h->timings[1] = ms;
+    if (*h->flag_host) return MAS_NOT_SPD;
+    h->built = true;
+    return MAS_OK;
+}
+
+int mas_apply(mas_handle* h, const double* r, double* z, void* stream) {
+    if (!h || !h->analyzed || !h->built) return MAS_NOT_READY;
+    if (!r || !z || r == z) return MAS_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const SolverView v = view(h);
+    const bool mixed = h->opts.precision == MAS_PRECISION_MIXED;
+    HIP_TRY(launch_perm_in(v, r, v.r, s));
+    if (v.L > 1) HIP_TRY(launch_update(v, true, mixed, s));
+    HIP_TRY(launch_apply_coarse(v, mixed, kApplyPlain, s));
+    HIP_TRY(launch_apply_level0(v, mixed, kApplyPlain, s));
+    HIP_TRY(launch_perm_out(v, v.z, z, s));
+    return MAS_OK;
+}
+
+int bcsr_spmv(const mas_bcsr* H, const double* x, double* y, void* stream) {
+    if (!H || !x || !y || x == y) return MAS_INVALID_ARG;
+    if (H->n_rows < 0 || H->nnzb < 0 || (H->dtype != MAS_F64 && H->dtype != MAS_F32)) return MAS_INVALID_ARG;
+    if (H->n_rows == 0) return MAS_OK;
+    if (!H->row_ptr || !H->col_idx || (H->nnzb > 0 && !H->val)) return MAS_INVALID_ARG;
+    HIP_TRY(launch_spmv_user(H->n_rows, H->row_ptr, H->col_idx, H->val, H->dtype == MAS_F32, x, y,
+                             static_cast<hipStream_t>(stream)));
+    return MAS_OK;
+}
+
+int pcg_solve(mas_handle* h, const mas_bcsr* H, const double* b, double* x, const pcg_options* opts, pcg_result* res,
+              void* stream) {
+    const int rc = solve_impl(h, H, b, x, opts, res, static_cast<hipStream_t>(stream));
+    if (res && rc != res->status) res->status = rc;
+    return rc;
+}
+
+int pcg_adjoint(mas_handle* h, const mas_bcsr* H, const double* x, const double* dLdx, double* lambda, void* dLdH,
+                int32_t dLdH_dtype, const pcg_options* opts, pcg_result* res, void* stream) {
+    if (!x || !dLdx || !lambda || x == lambda || dLdx == lambda) return MAS_INVALID_ARG;
+    if (dLdH && dLdH_dtype != MAS_F64 && dLdH_dtype != MAS_F32) return MAS_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int rc = solve_impl(h, H, dLdx, lambda, opts, res, s);
+    if (rc < 0) return rc;
+    if (dLdH) {
+        HIP_TRY(launch_adjoint_scatter(H->n_rows, H->row_ptr, H->col_idx, lambda, x, dLdH, dLdH_dtype == MAS_F32, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    return rc;
+}
+
+int mas_get_info(const mas_handle* h, mas_info* out) {
+    if (!h || !out) return MAS_INVALID_ARG;
+    if (!h->analyzed) return MAS_NOT_READY;
+    const Plan& P = h->plan;
+    std::memset(out, 0, sizeof(*out));
+    out->n_rows = P.V;
+    out->nnzb = P.nnzb;
+    out->domain_size = P.N;
+    out->parts = P.M;
+    out->slack = P.No;
+    out->levels = P.L;
+    for (int l = 0; l < P.L; ++l) {
+        out->units[l] = P.units[l];
+        out->domains[l] = P.ndom[l];
+        out->coarse_nnzb[l] = l == 0 ? P.nnzb : static_cast<int>(P.ciA[l].size());
+    }
+    out->workspace_bytes = static_cast<int64_t>(h->lay.total);
+    out->inverse_bytes = static_cast<int64_t>(h->lay.inverse_bytes);
+    return MAS_OK;
+}
+
+int mas_get_ordering(const mas_handle* h, int32_t* map, int32_t* remap, int32_t* sn) {
+    if (!h) return MAS_INVALID_ARG;
+    if (!h->analyzed) return MAS_NOT_READY;
+    const Plan& P = h->plan;
+    if (map) std::memcpy(map, P.map.data(), sizeof(int) * P.map.size());
+    if (remap) std::memcpy(remap, P.remap.data(), sizeof(int) * P.remap.size());
+    if (sn) std::memcpy(sn, P.sn.data(), sizeof(int) * P.sn.size());
+    return MAS_OK;
+}
+
+int mas_get_timings(const mas_handle* h, double* ms4) {
+    if (!h || !ms4) return MAS_INVALID_ARG;
+    for (int k = 0; k < 4; ++k) ms4[k] = h->timings[k];
+    return MAS_OK;
+}
+
+int mas_set_kernel_timing(mas_handle* h, int enable) {
+    if (!h) return MAS_INVALID_ARG;
+    h->kt.on = enable != 0;
+    for (int k = 0; k < kKSlots; ++k) {
+        h->kt.total_ms[k] = 0.0;
+        h->kt.launches[k] = 0;
+    }
+    h->kt.pending.clear();
+    h->kt.used = 0;
+    return MAS_OK;
+}
+
+int mas_get_kernel_timing(const mas_handle* h, double* total_ms, int32_t* launches) {
+    if (!h || !total_ms || !launches) return MAS_INVALID_ARG;
+    for (int k = 0; k < kKSlots; ++k) {
+        total_ms[k] = h->kt.total_ms[k];
+        launches[k] = h->kt.launches[k];
+    }
+    return MAS_OK;
+}
+
+const char* mas_status_string(int status) {
+    switch (status) {
+        case MAS_OK: return "ok";
+        case MAS_NOT_CONVERGED: return "not converged (max_iter reached)";
+        case MAS_INVALID_ARG: return "invalid argument";
+        case MAS_NOT_SPD: return "matrix not symmetric positive definite";
+        case MAS_HIP_ERROR: return "HIP runtime error";
+        case MAS_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case MAS_NOT_READY: return "handle not ready (analyze, then build)";
+        case MAS_NOT_FINITE: return "non-finite residual";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

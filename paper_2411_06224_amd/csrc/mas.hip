@@ -1,0 +1,426 @@
+// MAS preconditioner on the device: coarse matrices, batched domain
+// inversion and the apply (Supp. Eq. 4-6; algorithm "Compute MAS
+// preconditioner" in Sec. 3.3).
+#include "launch.hpp"
+
+namespace maspcg {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------ coarse sums
+// A_l = C H C^T by levels (Supp. Eq. 5: A_(l) = C A C^T with unit 3x3
+// weights).  Each coarse block owns a list of fine blocks and sums it in a
+// fixed order: no atomics, bitwise reproducible.
+
+__global__ void __launch_bounds__(256) k_coarse_sum_first(int nnzA, const int* __restrict__ ptr,
+                                                           const int* __restrict__ src, const double* __restrict__ Hu,
+                                                           double* __restrict__ A) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nnzA) return;
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = ptr[t]; q < ptr[t + 1]; ++q) {
+        const double* blk = Hu + 9LL * src[q];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) s[c] += blk[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A[(long long)c * nnzA + t] = s[c];
+}
+
+__global__ void __launch_bounds__(256) k_coarse_sum_next(int nnzA, int nnzPrev, const int* __restrict__ ptr,
+                                                          const int* __restrict__ src, const double* __restrict__ Ap,
+                                                          double* __restrict__ A) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= nnzA) return;
+    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int q = ptr[t]; q < ptr[t + 1]; ++q) {
+        const int k = src[q];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) s[c] += Ap[(long long)c * nnzPrev + k];
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A[(long long)c * nnzA + t] = s[c];
+}
+
+// ------------------------------------------------------- domain inversion
+// One 64-lane wave per domain (all levels in one launch).  The domain
+// matrix (3N x 3N, padded to 16T with identity rows on empty lanes so that
+// the inverse of the occupied part comes out directly) sits in LDS and is
+// inverted in place by block Gauss-Jordan over 16x16 tiles:
+//   P = inv(A_kk) (register-resident scalar Gauss-Jordan, 16 pivots),
+//   A_kj <- P A_kj, A_ij <- A_ij - A_ik A_kj, A_ik <- -A_ik P, A_kk <- P,
+// with the tile products on v_mfma_f64_16x16x4f64.  Pivots are Schur
+// complement diagonals of an SPD matrix; a pivot <= 0 flags NOT_SPD.
+//
+// MFMA f64 16x16x4 lane layout on gfx950: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; result register v of lane l is D[l / 16 + 4 v][l % 16].
+
+struct DomTable {
+    int off[kMaxLv + 1];  // first workgroup of each level
+};
+
+__device__ __forceinline__ int level_of(const DomTable& tab, int L, int g) {
+    int l = 0;
+    while (l + 1 < L && g >= tab.off[l + 1]) ++l;
+    return l;
+}
+
+template <int T>
+__global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __restrict__ Hu, int want32, DomTable tab) {
+    constexpr int NP = 16 * T;
+    constexpr int LD = NP + 1;  // odd stride: a 16-row column read hits 16 distinct bank pairs
+    __shared__ double A[NP * LD];
+    const int lane = threadIdx.x;
+    const int l = level_of(tab, B.L, blockIdx.x);
+    const int d = blockIdx.x - tab.off[l];
+    const int N = B.N, n = 3 * N;
+
+    for (int e = lane; e < NP * LD; e += 64) A[e] = 0.0;
+    __syncthreads();
+
+    // gather the upper in-domain blocks and mirror them
+    const int* dptr = B.dom_ptr[l];
+    for (int q = dptr[d] + lane; q < dptr[d + 1]; q += 64) {
+        const int k = B.dom_blk[l][q];
+        const int ab = B.dom_ab[l][q];
+        const int a = ab & 255, b = ab >> 8;
+        double v[9];
+        if (l == 0) {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) v[c] = Hu[9LL * k + c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 9; ++c) v[c] = B.A[l][(long long)c * B.nnzA[l] + k];
+        }
+        if (a == b) {
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = r; c < 3; ++c) {
+                    A[(3 * a + r) * LD + 3 * a + c] = v[3 * r + c];
+                    A[(3 * a + c) * LD + 3 * a + r] = v[3 * r + c];
+                }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    A[(3 * a + r) * LD + 3 * b + c] = v[3 * r + c];
+                    A[(3 * b + c) * LD + 3 * a + r] = v[3 * r + c];
+                }
+        }
+    }
+    // occupied lanes of this domain as a bit mask
+    bool occ_lane = false;
+    if (lane < N) {
+        const int u = d * N + lane;
+        occ_lane = (l == 0) ? (B.remap[u] >= 0) : (u < B.units[l]);
+    }
+    const unsigned long long occ = __ballot(occ_lane);
+    __syncthreads();
+    for (int p = lane; p < NP; p += 64) {
+        const bool live = p < n && ((occ >> (p / 3)) & 1ull);
+        if (!live) A[p * LD + p] = 1.0;
+    }
+    __syncthreads();
+
+    const int c16 = lane & 15, g4 = lane >> 4;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < T; ++k) {
+        const int base = 16 * k;
+        // ---- P = inv(A_kk): lane holds column c16, rows 4 g4 + v
+        double a[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a[v] = A[(base + 4 * g4 + v) * LD + base + c16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int jg = j >> 2, jv = j & 3;
+            const double aj = a[jv];
+            const double piv = __shfl(aj, jg * 16 + j);
+            const double rowj = __shfl(aj, jg * 16 + c16);
+            double colj[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) colj[v] = __shfl(a[v], g4 * 16 + j);
+            ok = ok && (piv > 0.0) && finite(piv);
+            const double inv = 1.0 / piv;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 4 * g4 + v;
+                if (i == j)
+                    a[v] = (c16 == j) ? inv : a[v] * inv;
+                else
+                    a[v] = (c16 == j) ? -colj[v] * inv : a[v] - colj[v] * rowj * inv;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(base + 4 * g4 + v) * LD + base + c16] = a[v];
+        __syncthreads();
+        // ---- row panel: A_kj <- P A_kj
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            if (j == k) continue;
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const double av = A[(base + c16) * LD + base + 4 * kk + g4];
+                const double bv = A[(base + 4 * kk + g4) * LD + 16 * j + c16];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A[(base + g4 + 4 * v) * LD + 16 * j + c16] = acc[v];
+        }
+        __syncthreads();
+        // ---- trailing update: A_ij <- A_ij - A_ik A_kj
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            if (i == k) continue;
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                if (j == k) continue;
+                v4d acc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[v] = A[(16 * i + g4 + 4 * v) * LD + 16 * j + c16];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const double av = -A[(16 * i + c16) * LD + base + 4 * kk + g4];
+                    const double bv = A[(base + 4 * kk + g4) * LD + 16 * j + c16];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) A[(16 * i + g4 + 4 * v) * LD + 16 * j + c16] = acc[v];
+            }
+        }
+        __syncthreads();
+        // ---- column panel: A_ik <- -A_ik P
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            if (i == k) continue;
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const double av = -A[(16 * i + c16) * LD + base + 4 * kk + g4];
+                const double bv = A[(base + 4 * kk + g4) * LD + base + c16];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) A[(16 * i + g4 + 4 * v) * LD + base + c16] = acc[v];
+        }
+        __syncthreads();
+    }
+    if (!ok && lane == 0) atomicOr(B.flag, 1);
+
+    // column-major n x n, zero rows/columns on empty lanes
+    const long long off = (long long)d * n * n;
+    double* o64 = B.inv64[l] + off;
+    float* o32 = want32 ? B.inv32[l] + off : nullptr;
+    for (int e = lane; e < n * n; e += 64) {
+        const int col = e / n, row = e - col * n;
+        const bool live = ((occ >> (row / 3)) & 1ull) && ((occ >> (col / 3)) & 1ull);
+        const double val = live ? A[row * LD + col] : 0.0;
+        o64[e] = val;
+        if (o32) o32[e] = static_cast<float>(val);
+    }
+}
+
+// ------------------------------------------------------------------ apply
+// Coarse levels l >= 1 (one workgroup per domain, all levels in one launch):
+// r_l for the domain's N units (level 1 straight from r_1, higher levels as
+// sums over the level-1 supernodes below each unit, one wave per unit),
+// then y_l = Inv_{l,d} r_l.
+
+template <typename TI>
+__global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab, int check_done) {
+    __shared__ double rl[128];
+    if (check_done && v.st->done) return;
+    int l = 1;
+    while (l + 1 < v.L && blockIdx.x >= tab.off[l + 1]) ++l;
+    const int d = blockIdx.x - tab.off[l];
+    const int N = v.N, n = 3 * N;
+    const int u0 = d * N;
+    const int nu = min(N, v.units[l] - u0);
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    if (l == 1) {
+        if (t < n) rl[t] = t < 3 * nu ? v.r1[3 * u0 + t] : 0.0;
+    } else {
+        const int* mp = v.mem_ptr[l];
+        const int* mi = v.mem_idx[l];
+        for (int a = w; a < N; a += 4) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            if (a < nu) {
+                for (int m = mp[u0 + a] + lane; m < mp[u0 + a + 1]; m += 64) {
+                    const int k = mi[m];
+                    s0 += v.r1[3 * k];
+                    s1 += v.r1[3 * k + 1];
+                    s2 += v.r1[3 * k + 2];
+                }
+            }
+            s0 = wave_sum(s0);
+            s1 = wave_sum(s1);
+            s2 = wave_sum(s2);
+            if (lane == 0) {
+                rl[3 * a] = s0;
+                rl[3 * a + 1] = s1;
+                rl[3 * a + 2] = s2;
+            }
+        }
+    }
+    __syncthreads();
+    if (t < n) {
+        const TI* inv;
+        if constexpr (sizeof(TI) == 8)
+            inv = v.inv64[l];
+        else
+            inv = v.inv32[l];
+        inv += (long long)d * n * n;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < n; ++k) acc += static_cast<double>(inv[k * n + t]) * rl[k];
+        v.y[l][3 * u0 + t] = acc;
+    }
+}
+
+// Level 0: z = Inv_{0,d} r_d + sum_{l >= 1} y_l[unit of the slot at level l]
+// (prolongation of every coarse level, Supp. Eq. 6), with r^T z.  One wave
+// per domain when 3N <= 64, two otherwise.
+template <typename TI, int kMode>
+__global__ void __launch_bounds__(256) k_apply_level0(SolverView v) {
+    __shared__ double rs[4][64];
+    __shared__ double scratch[4];
+    if (kMode != kApplyPlain && v.st->done) return;
+    const int N = v.N, n = 3 * N;
+    const int W = n > 64 ? 2 : 1;  // waves per domain
+    const int per = 4 / W;         // domains per workgroup
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int slot_in_wg = w / W;
+    const int tl = (w % W) * 64 + lane;  // row of the domain this lane computes
+    const int d = blockIdx.x * per + slot_in_wg;
+    const bool live = d < v.M && tl < n;
+    double* rsd = &rs[0][0] + slot_in_wg * 64 * W;
+    const long long base = 3LL * N * d;
+    double rv = 0.0;
+    if (live) {
+        rv = v.r[base + tl];
+        rsd[tl] = rv;
+    }
+    __syncthreads();
+    double zv = 0.0;
+    if (live) {
+        const TI* inv;
+        if constexpr (sizeof(TI) == 8)
+            inv = v.inv64[0];
+        else
+            inv = v.inv32[0];
+        inv += (long long)d * n * n;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < n; ++k) acc += static_cast<double>(inv[k * n + tl]) * rsd[k];
+        const int slot = d * N + tl / 3, c = tl % 3;
+        for (int l = 1; l < v.L; ++l) {
+            const int u = v.anc[(long long)(l - 1) * v.NS + slot];
+            if (u >= 0) acc += v.y[l][3 * u + c];
+        }
+        zv = acc;
+        v.z[base + tl] = zv;
+    }
+    if (kMode == kApplyPlain) return;
+    double in[1] = {rv * zv}, out[1];
+    if (grid_reduce<1>(in, v.partials, &v.st->counter[kCntApply], out, scratch) && threadIdx.x == 0) {
+        DevState* st = v.st;
+        if (!finite(out[0])) {
+            st->status = -6;
+            st->done = 1;
+        } else if (kMode == kApplyInit) {
+            st->rho = out[0];
+            st->beta = 0.0;
+        } else {
+            st->beta = out[0] / st->rho;
+            st->rho = out[0];
+        }
+    }
+}
+
+DomTable make_table(const int* ndom, int first, int L) {
+    DomTable t{};
+    int acc = 0;
+    for (int l = 0; l <= kMaxLv; ++l) t.off[l] = 0;
+    for (int l = first; l < L; ++l) {
+        t.off[l] = acc;
+        acc += ndom[l];
+    }
+    for (int l = L; l <= kMaxLv; ++l) t.off[l] = acc;
+    return t;
+}
+
+template <int T>
+void launch_invert_t(const BuildView& b, const double* Hu, bool want32, int total, const DomTable& tab, hipStream_t s) {
+    hipLaunchKernelGGL(k_invert<T>, dim3(total), dim3(64), 0, s, b, Hu, want32 ? 1 : 0, tab);
+}
+
+}  // namespace
+
+int grid_apply0(int M, int N) { return ceil_div(M, 3 * N > 64 ? 2 : 4); }
+
+hipError_t launch_coarse_sums(const BuildView& b, const double* Hu, hipStream_t s) {
+    for (int l = 1; l < b.L; ++l) {
+        const int g = ceil_div(b.nnzA[l], 256);
+        if (g == 0) continue;
+        if (l == 1)
+            hipLaunchKernelGGL(k_coarse_sum_first, dim3(g), dim3(256), 0, s, b.nnzA[1], b.red_ptr[1], b.red_src[1], Hu,
+                               b.A[1]);
+        else
+            hipLaunchKernelGGL(k_coarse_sum_next, dim3(g), dim3(256), 0, s, b.nnzA[l], b.nnzA[l - 1], b.red_ptr[l],
+                               b.red_src[l], b.A[l - 1], b.A[l]);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_invert(const BuildView& b, const double* Hu, bool want32, hipStream_t s) {
+    const DomTable tab = make_table(b.ndom, 0, b.L);
+    const int total = tab.off[kMaxLv];
+    const int T = ceil_div(3 * b.N, 16);
+    switch (T) {
+        case 1: launch_invert_t<1>(b, Hu, want32, total, tab, s); break;
+        case 2: launch_invert_t<2>(b, Hu, want32, total, tab, s); break;
+        case 3: launch_invert_t<3>(b, Hu, want32, total, tab, s); break;
+        case 4: launch_invert_t<4>(b, Hu, want32, total, tab, s); break;
+        case 5: launch_invert_t<5>(b, Hu, want32, total, tab, s); break;
+        case 6: launch_invert_t<6>(b, Hu, want32, total, tab, s); break;
+        case 7: launch_invert_t<7>(b, Hu, want32, total, tab, s); break;
+        case 8: launch_invert_t<8>(b, Hu, want32, total, tab, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, hipStream_t s) {
+    if (v.L < 2) return hipSuccess;
+    const DomTable tab = make_table(v.ndom, 1, v.L);
+    const int total = tab.off[kMaxLv];
+    const int check = mode == kApplyPlain ? 0 : 1;
+    if (f32)
+        hipLaunchKernelGGL(k_apply_coarse<float>, dim3(total), dim3(256), 0, s, v, tab, check);
+    else
+        hipLaunchKernelGGL(k_apply_coarse<double>, dim3(total), dim3(256), 0, s, v, tab, check);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, hipStream_t s) {
+    dim3 g(grid_apply0(v.M, v.N)), b(256);
+    if (f32) {
+        if (mode == kApplyPlain) hipLaunchKernelGGL((k_apply_level0<float, kApplyPlain>), g, b, 0, s, v);
+        else if (mode == kApplyInit) hipLaunchKernelGGL((k_apply_level0<float, kApplyInit>), g, b, 0, s, v);
+        else hipLaunchKernelGGL((k_apply_level0<float, kApplyIter>), g, b, 0, s, v);
+    } else {
+        if (mode == kApplyPlain) hipLaunchKernelGGL((k_apply_level0<double, kApplyPlain>), g, b, 0, s, v);
+        else if (mode == kApplyInit) hipLaunchKernelGGL((k_apply_level0<double, kApplyInit>), g, b, 0, s, v);
+        else hipLaunchKernelGGL((k_apply_level0<double, kApplyIter>), g, b, 0, s, v);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace maspcg

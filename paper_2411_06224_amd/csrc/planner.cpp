@@ -1,0 +1,399 @@
+// Host-side symbolic analysis (see planner.hpp).
+//
+// Ordering (Sec. 3.2): the node graph is partitioned into
+// M = ceil(V / (N - N_o)) parts of at most N nodes, the slack N_o searched
+// upward from 0 (Eq. num_subdomains).  The paper uses METIS; here the
+// partitioner is a recursive BFS bisection with fully specified tie-breaks
+// so that an independent implementation reproduces it bit for bit:
+//   split(S, k): k == 1 -> S is the next part; otherwise kL = k/2,
+//   nL = floor(|S| kL / k) and S is cut after its first nL nodes in
+//   pseudo-peripheral BFS order (start at the smallest id, twice jump to the
+//   smallest id on the deepest BFS level, then the BFS visit order with
+//   ascending neighbours, restarting at the smallest unvisited id).
+// Part p occupies slots [pN, pN + N) in ascending node order; the rest of
+// its slots are padding (-1), one part per MAS domain (Fig. mapping).
+//
+// Hierarchy (Sec. 3.1, Supp. Alg. 2-5): at each level the units of a domain
+// that are coupled by stored blocks form connected components; each
+// component is a supernode of the next level, numbered inside its domain by
+// its lowest lane and globally by domain order.  N consecutive supernodes
+// form a domain of the next level.  Construction stops at a single domain,
+// at max_levels, or when no component merges two units.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+namespace maspcg {
+namespace {
+
+struct Graph {
+    std::vector<int> off, nbr;
+};
+
+Graph symmetrize(int V, const int32_t* ptr, const int32_t* adj) {
+    std::vector<std::pair<int, int>> e;
+    e.reserve(ptr ? 2 * static_cast<size_t>(ptr[V]) : 0);
+    for (int i = 0; i < V; ++i)
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+            int j = adj[p];
+            if (j < 0 || j >= V || j == i) continue;
+            e.emplace_back(i, j);
+            e.emplace_back(j, i);
+        }
+    std::sort(e.begin(), e.end());
+    e.erase(std::unique(e.begin(), e.end()), e.end());
+    Graph g;
+    g.off.assign(V + 1, 0);
+    g.nbr.resize(e.size());
+    for (size_t k = 0; k < e.size(); ++k) {
+        g.off[e[k].first + 1]++;
+        g.nbr[k] = e[k].second;
+    }
+    for (int i = 0; i < V; ++i) g.off[i + 1] += g.off[i];
+    return g;
+}
+
+class Bisection {
+  public:
+    explicit Bisection(const Graph& g) : g_(g), in_(g.off.size() - 1, -1), seen_(g.off.size() - 1, -1), depth_(g.off.size() - 1, 0) {}
+
+    // Fills part[] by recursive bisection of all nodes into k parts.
+    void run(int k, std::vector<int>& part) {
+        const int V = static_cast<int>(in_.size());
+        std::vector<int> nodes(V);
+        std::iota(nodes.begin(), nodes.end(), 0);
+        struct Task {
+            int lo, hi, k;
+        };
+        std::vector<Task> stack{{0, V, k}};
+        int next_part = 0;
+        while (!stack.empty()) {
+            Task t = stack.back();
+            stack.pop_back();
+            if (t.k == 1) {
+                for (int q = t.lo; q < t.hi; ++q) part[nodes[q]] = next_part;
+                ++next_part;
+                continue;
+            }
+            const int kl = t.k / 2;
+            const int n = t.hi - t.lo;
+            const int nl = static_cast<int>(static_cast<long long>(n) * kl / t.k);
+            if (n > 0) reorder(nodes.data() + t.lo, n);
+            // left half is emitted first: push it last
+            stack.push_back({t.lo + nl, t.hi, t.k - kl});
+            stack.push_back({t.lo, t.lo + nl, kl});
+        }
+    }
+
+  private:
+    // BFS inside the current set from root; appends visit order to out and
+    // records depths.  Returns the deepest level reached.
+    int bfs(int root, std::vector<int>& out) {
+        size_t head = out.size();
+        out.push_back(root);
+        seen_[root] = mark_;
+        depth_[root] = 0;
+        int deepest = 0;
+        while (head < out.size()) {
+            const int u = out[head++];
+            for (int p = g_.off[u]; p < g_.off[u + 1]; ++p) {
+                const int v = g_.nbr[p];
+                if (in_[v] != set_ || seen_[v] == mark_) continue;
+                seen_[v] = mark_;
+                depth_[v] = depth_[u] + 1;
+                deepest = std::max(deepest, depth_[v]);
+                out.push_back(v);
+            }
+        }
+        return deepest;
+    }
+
+    void reorder(int* S, int n) {
+        set_ = ++tag_;
+        for (int q = 0; q < n; ++q) in_[S[q]] = set_;
+        std::vector<int> asc(S, S + n);
+        std::sort(asc.begin(), asc.end());
+        int root = asc.front();
+        std::vector<int> visit;
+        visit.reserve(n);
+        for (int rep = 0; rep < 2; ++rep) {
+            mark_ = ++tag_;
+            visit.clear();
+            const int deepest = bfs(root, visit);
+            int best = -1;
+            for (int v : visit)
+                if (depth_[v] == deepest && (best < 0 || v < best)) best = v;
+            root = best;
+        }
+        mark_ = ++tag_;
+        visit.clear();
+        bfs(root, visit);
+        size_t scan = 0;
+        while (static_cast<int>(visit.size()) < n) {
+            while (seen_[asc[scan]] == mark_) ++scan;
+            bfs(asc[scan], visit);
+        }
+        std::copy(visit.begin(), visit.end(), S);
+    }
+
+    const Graph& g_;
+    std::vector<int> in_, seen_, depth_;
+    int tag_ = 0, set_ = -1, mark_ = -1;
+};
+
+// Components of the units of each domain under the block pattern (rp, ci)
+// over units.  Returns the next-level id of every unit (-1 if empty) and the
+// number of components.
+int components(int units, int N, const std::vector<int>& rp, const std::vector<int>& ci,
+               const std::vector<char>& occupied, std::vector<int>& comp) {
+    comp.assign(units, -1);
+    int next = 0;
+    std::vector<int> stack;
+    for (int d = 0; d * N < units; ++d) {
+        const int lo = d * N, hi = std::min(units, lo + N);
+        for (int u = lo; u < hi; ++u) {
+            if (!occupied[u] || comp[u] >= 0) continue;
+            const int id = next++;
+            comp[u] = id;
+            stack.assign(1, u);
+            while (!stack.empty()) {
+                const int s = stack.back();
+                stack.pop_back();
+                for (int p = rp[s]; p < rp[s + 1]; ++p) {
+                    const int t = ci[p];
+                    if (t < lo || t >= hi || comp[t] >= 0) continue;
+                    comp[t] = id;
+                    stack.push_back(t);
+                }
+            }
+        }
+    }
+    return next;
+}
+
+// Galerkin pattern and reduction plan: block (s, t) of the fine matrix goes
+// to block (up[s], up[t]) of the coarse one.
+void coarsen(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& up, int coarse_units,
+             std::vector<int>& rpC, std::vector<int>& ciC, std::vector<int>& red_ptr, std::vector<int>& red_src) {
+    const int fine_units = static_cast<int>(rp.size()) - 1;
+    const int nnz = rp.back();
+    std::vector<long long> key(nnz);
+    for (int s = 0; s < fine_units; ++s)
+        for (int p = rp[s]; p < rp[s + 1]; ++p)
+            key[p] = static_cast<long long>(up[s]) * coarse_units + up[ci[p]];
+    red_src.resize(nnz);
+    std::iota(red_src.begin(), red_src.end(), 0);
+    std::stable_sort(red_src.begin(), red_src.end(), [&](int a, int b) { return key[a] < key[b]; });
+    rpC.assign(coarse_units + 1, 0);
+    ciC.clear();
+    red_ptr.assign(1, 0);
+    for (int q = 0; q < nnz; ++q) {
+        const long long k = key[red_src[q]];
+        if (q == 0 || k != key[red_src[q - 1]]) {
+            if (q) red_ptr.push_back(q);
+            ciC.push_back(static_cast<int>(k % coarse_units));
+            rpC[k / coarse_units + 1]++;
+        }
+    }
+    red_ptr.push_back(nnz);
+    for (int s = 0; s < coarse_units; ++s) rpC[s + 1] += rpC[s];
+}
+
+void domain_plan(const std::vector<int>& rp, const std::vector<int>& ci, int units, int N, std::vector<int>& ptr,
+                 std::vector<int>& blk, std::vector<int>& ab) {
+    const int nd = (units + N - 1) / N;
+    ptr.assign(1, 0);
+    blk.clear();
+    ab.clear();
+    for (int d = 0; d < nd; ++d) {
+        const int lo = d * N, hi = std::min(units, lo + N);
+        for (int s = lo; s < hi; ++s)
+            for (int p = rp[s]; p < rp[s + 1]; ++p) {
+                const int t = ci[p];
+                if (t < s || t >= lo + N) continue;
+                blk.push_back(p);
+                ab.push_back((s - lo) | ((t - lo) << 8));
+            }
+        ptr.push_back(static_cast<int>(blk.size()));
+    }
+}
+
+}  // namespace
+
+std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* g_ptr,
+                    const int32_t* g_adj, int N, int max_levels, Plan& P) {
+    if (V <= 0 || nnzb < V || !row_ptr || !col_idx) return "empty matrix or null pattern";
+    if (N < 1 || N > 40) return "domain_size must be in [1, 40]";
+    if ((g_ptr == nullptr) != (g_adj == nullptr)) return "graph needs both g_ptr and g_adj";
+    if (row_ptr[0] != 0 || row_ptr[V] != nnzb) return "row_ptr must start at 0 and end at nnzb";
+    for (int i = 0; i < V; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return "row_ptr not monotone";
+        bool diag = false;
+        for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            const int j = col_idx[p];
+            if (j < 0 || j >= V) return "column index out of range";
+            if (p > row_ptr[i] && j <= col_idx[p - 1]) return "columns must be strictly ascending in a row";
+            diag |= (j == i);
+        }
+        if (!diag) return "every row needs its diagonal block";
+    }
+    for (int i = 0; i < V; ++i)
+        for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            const int j = col_idx[p];
+            if (!std::binary_search(col_idx + row_ptr[j], col_idx + row_ptr[j + 1], i)) return "pattern is not symmetric";
+        }
+    if (g_ptr) {
+        if (g_ptr[0] != 0) return "g_ptr must start at 0";
+        for (int i = 0; i < V; ++i)
+            if (g_ptr[i + 1] < g_ptr[i]) return "g_ptr not monotone";
+    }
+
+    P = Plan();
+    P.V = V;
+    P.N = N;
+    P.nnzb = nnzb;
+
+    // ---- partition with the slack search of Eq. num_subdomains
+    const Graph g = g_ptr ? symmetrize(V, g_ptr, g_adj) : symmetrize(V, row_ptr, col_idx);
+    P.part.assign(V, 0);
+    bool found = false;
+    for (int No = 0; No < N && !found; ++No) {
+        const int M = (V + (N - No) - 1) / (N - No);
+        Bisection(g).run(M, P.part);
+        std::vector<int> size(M, 0);
+        bool fits = true;
+        for (int i = 0; i < V; ++i) fits &= (++size[P.part[i]] <= N);
+        if (fits) {
+            P.M = M;
+            P.No = No;
+            found = true;
+        }
+    }
+    if (!found) return "partition failed";
+
+    // ---- slots (one part per domain, ascending node ids, -1 padding)
+    P.NS = P.M * N;
+    P.map.assign(V, -1);
+    P.remap.assign(P.NS, -1);
+    {
+        std::vector<int> fill(P.M, 0);
+        for (int i = 0; i < V; ++i) {
+            const int s = P.part[i] * N + fill[P.part[i]]++;
+            P.map[i] = s;
+            P.remap[s] = i;
+        }
+    }
+
+    // ---- H in slot order
+    P.rp0.assign(P.NS + 1, 0);
+    P.ci0.resize(nnzb);
+    P.perm_src.resize(nnzb);
+    for (int s = 0; s < P.NS; ++s) {
+        const int i = P.remap[s];
+        P.rp0[s + 1] = P.rp0[s] + (i >= 0 ? row_ptr[i + 1] - row_ptr[i] : 0);
+    }
+    {
+        std::vector<std::pair<int, int>> row;
+        for (int s = 0; s < P.NS; ++s) {
+            const int i = P.remap[s];
+            if (i < 0) continue;
+            row.clear();
+            for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) row.emplace_back(P.map[col_idx[p]], p);
+            std::sort(row.begin(), row.end());
+            for (size_t q = 0; q < row.size(); ++q) {
+                P.ci0[P.rp0[s] + q] = row[q].first;
+                P.perm_src[P.rp0[s] + q] = row[q].second;
+            }
+        }
+    }
+
+    // ---- hierarchy
+    P.units.push_back(P.NS);
+    P.ndom.push_back(P.M);
+    P.rpA.emplace_back();  // level 0 uses rp0 / ci0
+    P.ciA.emplace_back();
+    P.red_ptr.emplace_back();
+    P.red_src.emplace_back();
+    int occupied_count = V;
+    for (int l = 0;; ++l) {
+        if (P.ndom[l] == 1) break;
+        if (max_levels > 0 && l + 1 >= max_levels) break;
+        if (l + 1 >= kMaxLevels) break;
+        const std::vector<int>& rp = l == 0 ? P.rp0 : P.rpA[l];
+        const std::vector<int>& ci = l == 0 ? P.ci0 : P.ciA[l];
+        std::vector<char> occ(P.units[l], 1);
+        if (l == 0)
+            for (int s = 0; s < P.NS; ++s) occ[s] = P.remap[s] >= 0;
+        std::vector<int> comp;
+        const int S = components(P.units[l], N, rp, ci, occ, comp);
+        if (S == occupied_count) break;  // nothing merged
+        P.up.push_back(comp);
+        P.units.push_back(S);
+        P.ndom.push_back((S + N - 1) / N);
+        P.rpA.emplace_back();
+        P.ciA.emplace_back();
+        P.red_ptr.emplace_back();
+        P.red_src.emplace_back();
+        coarsen(rp, ci, comp, S, P.rpA[l + 1], P.ciA[l + 1], P.red_ptr[l + 1], P.red_src[l + 1]);
+        occupied_count = S;
+    }
+    P.L = static_cast<int>(P.units.size());
+
+    // ---- inversion plans
+    P.dom_ptr.resize(P.L);
+    P.dom_blk.resize(P.L);
+    P.dom_ab.resize(P.L);
+    for (int l = 0; l < P.L; ++l)
+        domain_plan(l == 0 ? P.rp0 : P.rpA[l], l == 0 ? P.ci0 : P.ciA[l], P.units[l], N, P.dom_ptr[l], P.dom_blk[l],
+                    P.dom_ab[l]);
+
+    // ---- restriction / prolongation plans
+    P.lead1.assign(P.NS, -1);
+    if (P.L > 1) {
+        for (int d = 0; d < P.M; ++d) {
+            int last = -1;  // ids inside a domain appear in increasing order of lowest lane
+            for (int a = 0; a < N; ++a) {
+                const int u = P.up[0][d * N + a];
+                if (u > last) {
+                    P.lead1[d * N + a] = u;
+                    last = u;
+                }
+            }
+        }
+    }
+    P.anc.assign(static_cast<size_t>(std::max(P.L - 1, 0)) * P.NS, -1);
+    for (int l = 1; l < P.L; ++l)
+        for (int s = 0; s < P.NS; ++s) {
+            const int below = l == 1 ? s : P.anc[static_cast<size_t>(l - 2) * P.NS + s];
+            P.anc[static_cast<size_t>(l - 1) * P.NS + s] = below < 0 ? -1 : P.up[l - 1][below];
+        }
+    P.mem_ptr.resize(P.L);
+    P.mem_idx.resize(P.L);
+    if (P.L > 2) {
+        std::vector<int> a(P.units[1]);
+        std::iota(a.begin(), a.end(), 0);
+        for (int l = 2; l < P.L; ++l) {
+            for (int& v : a) v = P.up[l - 1][v];
+            std::vector<int>& ptr = P.mem_ptr[l];
+            std::vector<int>& idx = P.mem_idx[l];
+            ptr.assign(P.units[l] + 1, 0);
+            for (int v : a) ptr[v + 1]++;
+            for (int u = 0; u < P.units[l]; ++u) ptr[u + 1] += ptr[u];
+            idx.resize(P.units[1]);
+            std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+            for (int t = 0; t < P.units[1]; ++t) idx[fill[a[t]]++] = t;
+        }
+    }
+
+    // ---- per-node units for reports
+    P.sn.assign(static_cast<size_t>(P.L) * V, -1);
+    for (int i = 0; i < V; ++i) {
+        P.sn[i] = P.map[i];
+        for (int l = 1; l < P.L; ++l) P.sn[static_cast<size_t>(l) * V + i] = P.anc[static_cast<size_t>(l - 1) * P.NS + P.map[i]];
+    }
+    return "";
+}
+
+}  // namespace maspcg

@@ -1,0 +1,58 @@
+// Host-side symbolic analysis for the MAS preconditioner: ordering, hierarchy
+// and every gather / reduction plan the device phases consume.  Runs once per
+// sparsity pattern (the paper reorders once at load, Sec. 3.2).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace maspcg {
+
+constexpr int kMaxLevels = 16;
+
+struct Plan {
+    int V = 0;      // nodes (block rows of H)
+    int N = 0;      // domain size
+    int M = 0;      // level-0 domains (partition parts)
+    int No = 0;     // slack of Eq. num_subdomains
+    int NS = 0;     // level-0 slots = M * N
+    int L = 0;      // levels
+    int nnzb = 0;
+
+    std::vector<int> part, map, remap;  // map[V] node -> slot, remap[NS] slot -> node or -1
+
+    // H permuted into slot order (rows and columns are slots):
+    // block k of the permuted matrix is block perm_src[k] of the caller's H.
+    std::vector<int> rp0, ci0, perm_src;
+
+    std::vector<int> units;  // per level: level 0 -> NS slots, l >= 1 -> supernodes
+    std::vector<int> ndom;   // per level
+    std::vector<std::vector<int>> up;  // up[l][unit of level l] -> unit of level l+1 (-1: empty slot)
+
+    // Coarse matrices A_l = C H C^T over level-l units, l = 1..L-1 (index l).
+    // A_l[t] = sum over k in [red_ptr[l][t], red_ptr[l][t+1]) of A_{l-1}[red_src[l][k]]
+    // with A_0 the permuted H.
+    std::vector<std::vector<int>> rpA, ciA, red_ptr, red_src;
+
+    // Inversion gather plan per level: the upper (a <= b) in-domain blocks of
+    // each domain: block index into A_l (or the permuted H at level 0), and
+    // the lane pair packed as a | (b << 8).
+    std::vector<std::vector<int>> dom_ptr, dom_blk, dom_ab;
+
+    // Restriction to level 1, per slot: the level-1 unit if this slot is the
+    // lowest lane of that unit in its domain (it sums the unit), else -1.
+    std::vector<int> lead1;
+    // Coarse restriction for l >= 2: level-l unit -> level-1 units below it.
+    std::vector<std::vector<int>> mem_ptr, mem_idx;
+    // Prolongation: unit of every slot at levels 1..L-1, [(l-1) * NS + slot], -1 = empty.
+    std::vector<int> anc;
+
+    std::vector<int> sn;  // [L * V] unit of each node per level (level 0 = slot), for reports
+};
+
+// Returns "" on success or a message describing the invalid input.
+std::string analyze(int n_rows, int nnzb, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* g_ptr,
+                    const int32_t* g_adj, int N, int max_levels, Plan& out);
+
+}  // namespace maspcg

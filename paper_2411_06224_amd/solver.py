@@ -1,0 +1,278 @@
+"""Python front end of libmaspcg: argument marshalling over the C ABI.
+
+PyTorch provides device memory (every tensor below lives on the current HIP
+device) and the stream (torch's current stream); all arithmetic runs in the
+library's HIP kernels.  Nothing here computes on the host.
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (
+    MAS_F32,
+    MAS_F64,
+    MAS_NOT_CONVERGED,
+    MAS_OK,
+    MAS_PRECISION_F64,
+    MAS_PRECISION_MIXED,
+    MasBcsr,
+    MasInfo,
+    MasOptions,
+    PcgOptions,
+    PcgResult,
+    check,
+)
+
+_ALIGN = 256
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need_cuda(t, name, dtype=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a HIP device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class BlockMatrix:
+    """3x3-block CSR matrix on the device (layout of include/mas_pcg.h)."""
+
+    def __init__(self, row_ptr, col_idx, val):
+        _need_cuda(row_ptr, "row_ptr", torch.int32)
+        _need_cuda(col_idx, "col_idx", torch.int32)
+        _need_cuda(val, "val")
+        if val.dtype not in (torch.float64, torch.float32):
+            raise ValueError("val must be float64 or float32")
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+        self.n_rows = row_ptr.numel() - 1
+        self.nnzb = col_idx.numel()
+        if val.numel() != 9 * self.nnzb:
+            raise ValueError("val must hold nnzb 3x3 blocks")
+
+    @classmethod
+    def from_numpy(cls, row_ptr, col_idx, val, device="cuda", dtype=torch.float64):
+        return cls(
+            torch.as_tensor(np.asarray(row_ptr, dtype=np.int32), device=device),
+            torch.as_tensor(np.asarray(col_idx, dtype=np.int32), device=device),
+            torch.as_tensor(np.ascontiguousarray(val).reshape(-1, 3, 3), device=device).to(dtype),
+        )
+
+    def c_struct(self):
+        return MasBcsr(
+            self.n_rows,
+            self.nnzb,
+            self.row_ptr.data_ptr(),
+            self.col_idx.data_ptr(),
+            self.val.data_ptr(),
+            MAS_F32 if self.val.dtype == torch.float32 else MAS_F64,
+        )
+
+
+def bcsr_spmv(H, x, out=None):
+    """y = H x (FP64 vectors, FP64 or FP32 blocks)."""
+    _need_cuda(x, "x", torch.float64)
+    if x.numel() != 3 * H.n_rows:
+        raise ValueError("x must have 3 * n_rows entries")
+    y = torch.empty_like(x) if out is None else out
+    _need_cuda(y, "out", torch.float64)
+    L = _lib.load()
+    h = H.c_struct()
+    check("bcsr_spmv", L.bcsr_spmv(ctypes.byref(h), _ptr(x), _ptr(y), _stream()))
+    return y
+
+
+class MasPcg:
+    """MAS-preconditioned PCG for one sparsity pattern.
+
+    ``MasPcg(row_ptr, col_idx, graph=None, domain_size=16, max_levels=0,
+    precision="f64")`` runs the symbolic analysis on host copies of the
+    pattern (numpy arrays or CPU tensors); ``graph=(g_ptr, g_adj)`` is the
+    node graph to partition (default: the pattern of H).
+    """
+
+    def __init__(self, row_ptr, col_idx, graph=None, domain_size=16, max_levels=0, precision="f64", poison=False):
+        """``poison=True`` fills a new workspace with 0xFF bytes (NaN doubles) so
+        that any read of memory the library did not write shows up."""
+        self._poison = poison
+        L = _lib.load()
+        self._L = L
+        prec = {"f64": MAS_PRECISION_F64, "mixed": MAS_PRECISION_MIXED}[precision]
+        self.precision = precision
+        opts = MasOptions(int(domain_size), int(max_levels), prec, 0)
+        h = ctypes.c_void_p()
+        check("mas_create", L.mas_create(ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        rp = np.ascontiguousarray(np.asarray(row_ptr), dtype=np.int32)
+        ci = np.ascontiguousarray(np.asarray(col_idx), dtype=np.int32)
+        n = rp.size - 1
+        if graph is not None:
+            gp = np.ascontiguousarray(np.asarray(graph[0]), dtype=np.int32)
+            ga = np.ascontiguousarray(np.asarray(graph[1]), dtype=np.int32)
+            if ga.size == 0:
+                ga = np.zeros(1, np.int32)
+            gpp, gap = gp.ctypes.data_as(ctypes.c_void_p), ga.ctypes.data_as(ctypes.c_void_p)
+        else:
+            gpp = gap = None
+        check(
+            "mas_analyze",
+            L.mas_analyze(h, n, ci.size, rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p), gpp, gap),
+        )
+        self.n_rows = n
+        self.nnzb = int(ci.size)
+        self._ws = None
+        self._ws_ptr = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.mas_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    # ------------------------------------------------------------ queries
+    def info(self):
+        inf = MasInfo()
+        check("mas_get_info", self._L.mas_get_info(self._h, ctypes.byref(inf)))
+        lv = inf.levels
+        return {
+            "n_rows": inf.n_rows,
+            "nnzb": inf.nnzb,
+            "domain_size": inf.domain_size,
+            "parts": inf.parts,
+            "slack": inf.slack,
+            "levels": lv,
+            "units": list(inf.units[:lv]),
+            "domains": list(inf.domains[:lv]),
+            "coarse_nnzb": list(inf.coarse_nnzb[:lv]),
+            "workspace_bytes": int(inf.workspace_bytes),
+            "inverse_bytes": int(inf.inverse_bytes),
+        }
+
+    def ordering(self):
+        """Host copies ``(map[V], remap[M*N], sn[levels, V])``."""
+        inf = self.info()
+        mp = np.empty(self.n_rows, np.int32)
+        rm = np.empty(inf["parts"] * inf["domain_size"], np.int32)
+        sn = np.empty((inf["levels"], self.n_rows), np.int32)
+        check(
+            "mas_get_ordering",
+            self._L.mas_get_ordering(
+                self._h, mp.ctypes.data_as(ctypes.c_void_p), rm.ctypes.data_as(ctypes.c_void_p), sn.ctypes.data_as(ctypes.c_void_p)
+            ),
+        )
+        return mp, rm, sn
+
+    def timings(self):
+        """Device ms of [coarse sums, inversion, H permute, PCG iterations] of the last calls."""
+        out = (ctypes.c_double * 4)()
+        check("mas_get_timings", self._L.mas_get_timings(self._h, out))
+        return list(out)
+
+    KERNEL_SLOTS = ("spmv", "update", "apply_coarse", "apply_level0", "update_p", "residual", "permute_H", "restrict")
+
+    def set_kernel_timing(self, enable=True):
+        check("mas_set_kernel_timing", self._L.mas_set_kernel_timing(self._h, int(bool(enable))))
+
+    def kernel_timing(self):
+        """{slot: (total_ms, launches)} accumulated since set_kernel_timing."""
+        tot = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int32 * 8)()
+        check("mas_get_kernel_timing", self._L.mas_get_kernel_timing(self._h, tot, cnt))
+        return {k: (tot[i], cnt[i]) for i, k in enumerate(self.KERNEL_SLOTS)}
+
+    def workspace_size(self):
+        return int(self._L.mas_workspace_size(self._h))
+
+    # ------------------------------------------------------------- phases
+    def _workspace(self, device):
+        need = self.workspace_size()
+        if self._ws is None or self._ws.numel() < need + _ALIGN or self._ws.device != device:
+            self._ws = torch.empty(need + _ALIGN, dtype=torch.uint8, device=device)
+            if self._poison:
+                self._ws.fill_(255)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + _ALIGN - 1) // _ALIGN * _ALIGN
+        return self._ws_ptr, need
+
+    def build(self, H):
+        """Numeric phase on the device: coarse matrices and domain inverses."""
+        if H.val.dtype != torch.float64:
+            raise ValueError("mas_build needs FP64 values")
+        ptr, need = self._workspace(H.val.device)
+        h = H.c_struct()
+        check("mas_build", self._L.mas_build(self._h, ctypes.byref(h), ctypes.c_void_p(ptr), need, _stream()))
+        return self
+
+    def apply(self, r, out=None):
+        """z = M^-1 r."""
+        _need_cuda(r, "r", torch.float64)
+        z = torch.empty_like(r) if out is None else out
+        check("mas_apply", self._L.mas_apply(self._h, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    @staticmethod
+    def _opts(tol, max_iter, x0_given, replace_every, check_every):
+        return PcgOptions(float(tol), int(max_iter), int(x0_given), int(replace_every), int(check_every))
+
+    @staticmethod
+    def _result(res):
+        return {
+            "status": res.status,
+            "iterations": res.iterations,
+            "rel_residual": res.rel_residual,
+            "true_rel_residual": res.true_rel_residual,
+        }
+
+    def solve(self, H, b, tol=1e-4, max_iter=10000, x0=None, out=None, replace_every=50, check_every=8, allow_not_converged=True):
+        """Returns ``(x, result)``; raises MasError on failure."""
+        _need_cuda(b, "b", torch.float64)
+        x = out if out is not None else torch.empty_like(b)
+        if x0 is not None:
+            x.copy_(x0)
+        opts = self._opts(tol, max_iter, x0 is not None, replace_every, check_every)
+        res = PcgResult()
+        h = H.c_struct()
+        rc = self._L.pcg_solve(self._h, ctypes.byref(h), _ptr(b), _ptr(x), ctypes.byref(opts), ctypes.byref(res), _stream())
+        check("pcg_solve", rc, (MAS_OK, MAS_NOT_CONVERGED) if allow_not_converged else (MAS_OK,))
+        return x, self._result(res)
+
+    def adjoint(self, H, x, dLdx, dLdH_dtype=torch.float64, want_dH=True, tol=1e-4, max_iter=10000, replace_every=50, check_every=8):
+        """Returns ``(lambda = dL/db, dL/dH blocks or None, result)``."""
+        _need_cuda(x, "x", torch.float64)
+        _need_cuda(dLdx, "dLdx", torch.float64)
+        lam = torch.empty_like(dLdx)
+        dH = None
+        if want_dH:
+            if dLdH_dtype not in (torch.float64, torch.float32):
+                raise ValueError("dLdH_dtype must be float64 or float32")
+            dH = torch.empty((H.nnzb, 3, 3), dtype=dLdH_dtype, device=x.device)
+        opts = self._opts(tol, max_iter, 0, replace_every, check_every)
+        res = PcgResult()
+        h = H.c_struct()
+        rc = self._L.pcg_adjoint(
+            self._h,
+            ctypes.byref(h),
+            _ptr(x),
+            _ptr(dLdx),
+            _ptr(lam),
+            _ptr(dH),
+            MAS_F32 if dLdH_dtype == torch.float32 else MAS_F64,
+            ctypes.byref(opts),
+            ctypes.byref(res),
+            _stream(),
+        )
+        check("pcg_adjoint", rc, (MAS_OK, MAS_NOT_CONVERGED))
+        return lam, dH, self._result(res)

@@ -1,0 +1,354 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances:
+  SpMV (FP64)             |y - y_ref|_i <= 1e-14 (|H||x|)_i + tiny
+  MAS apply (FP64)        ||z - z_ref|| <= 1e-10 ||z_ref||
+  PCG, fixed iterations   ||x_k - x_k,ref|| <= 1e-10 ||x_k,ref||
+  PCG, converged          both meet tol on the true residual; iteration counts within +-2
+  tight solve             ||x - x_ref|| <= 1e-10 ||x_ref|| at tol 1e-13
+  mixed precision         true FP64 residual <= tol; error vs the FP64 oracle printed
+  gradients               vs dense FP64 gradient <= 1e-8 relative
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import cube, large_cube, small_cube
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2411_06224_amd as mp
+
+    mp.load()  # fail loudly if the library is missing
+    return torch.device("cuda:0")
+
+
+def _H(s, dev, dtype=torch.float64):
+    from paper_2411_06224_amd import BlockMatrix
+
+    return BlockMatrix.from_numpy(s.row_ptr, s.col_idx, s.val, device=dev, dtype=dtype)
+
+
+def _t(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+
+
+def _solver(s, N=16, max_levels=0, precision="f64", graph=True, poison=True):
+    """Workspaces start as NaN bit patterns: reading memory the library did
+    not write turns into a failure."""
+    from paper_2411_06224_amd import MasPcg
+
+    return MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj) if graph else None, domain_size=N,
+                  max_levels=max_levels, precision=precision, poison=poison)
+
+
+def _oracle(s, N=16, max_levels=0, graph=True):
+    if graph:
+        return oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels, gptr=s.gptr, gadj=s.gadj)
+    return oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels)
+
+
+def _absH_absx(s, x):
+    return oracle.spmv(s.row_ptr, s.col_idx, np.abs(s.val), np.abs(x))
+
+
+SYSTEMS = {
+    "cube1": lambda: cube(1),
+    "cube2": lambda: cube(2),
+    "cube3_stiff": lambda: cube(3, E=1e7, nu=0.45, seed=5),
+    "cube8": small_cube,
+    "rand300": lambda: synth.random_spd_system(300, 700, seed=2, local=12),
+    "contact6": lambda: cube(6, E=1e6, nu=0.49, seed=21, n_contacts=60),
+}
+
+
+# ------------------------------------------------------------------ SpMV ---
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spmv(dev, name, dtype):
+    from paper_2411_06224_amd import bcsr_spmv
+
+    _say("spmv", name, dtype)
+    s = SYSTEMS[name]()
+    x = np.random.default_rng(1).standard_normal(3 * s.n)
+    vals = s.val if dtype == "f64" else s.val.astype(np.float32).astype(np.float64)
+    H = _H(s, dev, torch.float64 if dtype == "f64" else torch.float32)
+    y = bcsr_spmv(H, _t(x, dev)).cpu().numpy()
+    ref = oracle.spmv(s.row_ptr, s.col_idx, vals, x)
+    bound = 1e-14 * oracle.spmv(s.row_ptr, s.col_idx, np.abs(vals), np.abs(x)) + 1e-300
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+def test_spmv_empty_rows_and_zero_sizes(dev):
+    from paper_2411_06224_amd import BlockMatrix, bcsr_spmv
+
+    _say("spmv empty rows")
+    rp = np.array([0, 0, 1, 1, 3, 3], np.int32)  # rows 0, 2, 4 empty
+    ci = np.array([1, 1, 3], np.int32)
+    val = np.random.default_rng(0).standard_normal((3, 3, 3))
+    H = BlockMatrix.from_numpy(rp, ci, val, device=dev)
+    x = np.random.default_rng(1).standard_normal(15)
+    y = bcsr_spmv(H, _t(x, dev)).cpu().numpy()
+    assert np.allclose(y, oracle.spmv(rp, ci, val, x), rtol=1e-14, atol=1e-14)
+    assert np.all(y[0:3] == 0) and np.all(y[6:9] == 0) and np.all(y[12:15] == 0)
+
+
+# ------------------------------------------------------------- MAS apply ---
+
+APPLY_CASES = [
+    ("cube1", 16, 0),
+    ("cube2", 4, 0),
+    ("cube3_stiff", 4, 0),
+    ("cube3_stiff", 1, 0),
+    ("cube8", 16, 2),
+    ("cube8", 16, 0),
+    ("cube8", 21, 0),
+    ("cube8", 32, 0),
+    ("cube8", 40, 0),
+    ("cube8", 7, 1),
+    ("rand300", 8, 0),
+    ("contact6", 16, 0),
+]
+
+
+@pytest.mark.parametrize("name,N,ml", APPLY_CASES)
+def test_mas_apply(dev, name, N, ml):
+    _say("mas_apply", name, N, ml)
+    s = SYSTEMS[name]()
+    P = _oracle(s, N, ml)
+    S = _solver(s, N, ml)
+    S.build(_H(s, dev))
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        r = rng.standard_normal(3 * s.n)
+        z = S.apply(_t(r, dev)).cpu().numpy()
+        ref = P.apply(r)
+        assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_mas_apply_dense_operator_tiny(dev):
+    _say("mas_apply dense operator cube2 N=4")
+    s = cube(2)
+    P = _oracle(s, 4)
+    S = _solver(s, 4)
+    S.build(_H(s, dev))
+    n = 3 * s.n
+    E = torch.eye(n, dtype=torch.float64, device=dev)
+    Z = torch.stack([S.apply(E[:, k].contiguous()) for k in range(n)], 1).cpu().numpy()
+    Zr = np.stack([P.apply(np.eye(n)[:, k]) for k in range(n)], 1)
+    assert np.linalg.norm(Z - Zr) <= 1e-10 * np.linalg.norm(Zr)
+    assert np.abs(Z - Z.T).max() <= 1e-12 * np.abs(Z).max()
+
+
+# ------------------------------------------------------------------- PCG ---
+
+
+@pytest.mark.parametrize("name,N", [("cube2", 4), ("cube3_stiff", 4), ("cube8", 16), ("rand300", 8), ("contact6", 16)])
+def test_pcg_fixed_iterations(dev, name, N):
+    _say("pcg fixed 10", name, N)
+    s = SYSTEMS[name]()
+    P = _oracle(s, N)
+    xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+    S = _solver(s, N)
+    H = _H(s, dev)
+    S.build(H)
+    x, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10)
+    assert res["iterations"] == it == 10 and res["status"] == 1
+    x = x.cpu().numpy()
+    assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
+@pytest.mark.parametrize("name,N,tol", [("cube8", 16, 1e-8), ("contact6", 16, 1e-6), ("rand300", 8, 1e-8), ("cube3_stiff", 4, 1e-10)])
+def test_pcg_converged(dev, name, N, tol):
+    _say("pcg converged", name, N, tol)
+    s = SYSTEMS[name]()
+    P = _oracle(s, N)
+    xr, st, it, rr, tr = P.pcg(s.b, tol=tol)
+    S = _solver(s, N)
+    H = _H(s, dev)
+    S.build(H)
+    x, res = S.solve(H, _t(s.b, dev), tol=tol)
+    assert res["status"] == 0 and st == 0
+    assert abs(res["iterations"] - it) <= 2
+    assert res["true_rel_residual"] <= tol * 1.01
+    xv = x.cpu().numpy()
+    true = np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) / np.linalg.norm(s.b)
+    assert true <= tol * 1.01
+
+
+def test_pcg_small_cube_tight(dev):
+    _say("pcg cube8 tol 1e-13")
+    s = small_cube()
+    P = _oracle(s, 16, 2)
+    xr, st, it, rr, tr = P.pcg(s.b, tol=1e-13)
+    S = _solver(s, 16, 2)
+    H = _H(s, dev)
+    S.build(H)
+    x, res = S.solve(H, _t(s.b, dev), tol=1e-13)
+    x = x.cpu().numpy()
+    assert res["status"] == 0
+    assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
+def test_pcg_edge_cases(dev):
+    from paper_2411_06224_amd import MasError
+
+    _say("pcg edge cases")
+    s = cube(2)
+    S = _solver(s, 4)
+    H = _H(s, dev)
+    S.build(H)
+    # b = 0 -> x = 0 after 0 iterations, also with a nonzero x0
+    x, res = S.solve(H, torch.zeros(3 * s.n, dtype=torch.float64, device=dev), x0=_t(np.ones(3 * s.n), dev))
+    assert res["status"] == 0 and res["iterations"] == 0 and not x.cpu().numpy().any()
+    # max_iter = 1 -> not converged with the first iterate
+    x, res = S.solve(H, _t(s.b, dev), tol=1e-12, max_iter=1)
+    xr, st, it, *_ = _oracle(s, 4).pcg(s.b, tol=1e-12, max_iter=1)
+    assert res["status"] == 1 and res["iterations"] == 1 and st == 1
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-12 * np.linalg.norm(xr)
+    # max_iter = 0 -> x = x0 = 0
+    x, res = S.solve(H, _t(s.b, dev), max_iter=0)
+    assert res["status"] == 1 and res["iterations"] == 0 and not x.cpu().numpy().any()
+    # warm start from the converged solution: 0 iterations
+    xs, _ = S.solve(H, _t(s.b, dev), tol=1e-10)
+    x, res = S.solve(H, _t(s.b, dev), tol=1e-8, x0=xs)
+    assert res["status"] == 0 and res["iterations"] == 0
+    # indefinite H: a flipped diagonal block fails the domain factorisation
+    val = s.val.copy()
+    dpos = [p for p in range(s.row_ptr[5], s.row_ptr[6]) if s.col_idx[p] == 5][0]
+    val[dpos] = -val[dpos] - np.eye(3)
+    Hb = _H(synth.BlockSystem(s.n, s.row_ptr, s.col_idx, val, s.b, s.gptr, s.gadj), dev)
+    with pytest.raises(MasError) as e:
+        S.build(Hb)
+    assert e.value.code == -2
+
+
+def test_pcg_single_domain_one_iteration(dev):
+    _say("pcg single domain")
+    s = cube(1)
+    S = _solver(s, 16)
+    H = _H(s, dev)
+    S.build(H)
+    x, res = S.solve(H, _t(s.b, dev), tol=1e-12)
+    assert res["iterations"] == 1 and res["status"] == 0
+    xs = np.linalg.solve(s.dense(), s.b)
+    assert np.linalg.norm(x.cpu().numpy() - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_pcg_deterministic(dev):
+    _say("pcg bitwise reproducible")
+    s = SYSTEMS["contact6"]()
+    S = _solver(s, 16)
+    H = _H(s, dev)
+    S.build(H)
+    x1, r1 = S.solve(H, _t(s.b, dev), tol=1e-8)
+    S.build(H)
+    x2, r2 = S.solve(H, _t(s.b, dev), tol=1e-8)
+    assert torch.equal(x1, x2) and r1 == r2
+
+
+# ----------------------------------------------------------------- mixed ---
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-6])
+def test_mixed_precision_small(dev, tol):
+    _say("mixed", tol)
+    s = small_cube()
+    xr, *_ = _oracle(s, 16).pcg(s.b, tol=1e-12)
+    S = _solver(s, 16, precision="mixed")
+    H = _H(s, dev)
+    S.build(H)
+    x, res = S.solve(H, _t(s.b, dev), tol=tol)
+    assert res["status"] == 0
+    xv = x.cpu().numpy()
+    true = np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) / np.linalg.norm(s.b)
+    assert true <= tol
+    print(f"mixed tol={tol}: its={res['iterations']} true_res={true:.3e} err_vs_fp64={np.linalg.norm(xv - xr) / np.linalg.norm(xr):.3e}")
+
+
+# ------------------------------------------------------------- gradients ---
+
+
+def test_adjoint_dense_gradient_small_cube(dev):
+    from paper_2411_06224_amd import mas_pcg_solve
+
+    _say("adjoint dense gradient cube8")
+    s = small_cube()
+    A = s.dense()
+    xt = np.random.default_rng(5).standard_normal(3 * s.n)
+    S = _solver(s, 16)
+    H = _H(s, dev)
+    val = H.val.clone().requires_grad_(True)
+    b = _t(s.b, dev).requires_grad_(True)
+    from paper_2411_06224_amd import BlockMatrix
+
+    Hg = BlockMatrix(H.row_ptr, H.col_idx, val)
+    x = mas_pcg_solve(S, Hg, b, tol=1e-12)
+    loss = 0.5 * ((x - _t(xt, dev)) ** 2).sum()
+    loss.backward()
+    xs = np.linalg.solve(A, s.b)
+    lam = np.linalg.solve(A, xs - xt)
+    gb = b.grad.cpu().numpy()
+    assert np.linalg.norm(gb - lam) <= 1e-8 * np.linalg.norm(lam)
+    G = val.grad.cpu().numpy()
+    Gr = oracle.adjoint_scatter(s.row_ptr, s.col_idx, lam, xs)
+    assert np.linalg.norm(G - Gr) <= 1e-8 * np.linalg.norm(Gr)
+
+
+def test_adjoint_matches_oracle_scatter_f32(dev):
+    _say("adjoint scatter f32")
+    s = SYSTEMS["contact6"]()
+    S = _solver(s, 16)
+    H = _H(s, dev)
+    S.build(H)
+    x, _ = S.solve(H, _t(s.b, dev), tol=1e-12)
+    g = np.random.default_rng(2).standard_normal(3 * s.n)
+    lam, dH, res = S.adjoint(H, x, _t(g, dev), dLdH_dtype=torch.float32, tol=1e-12)
+    lr, *_ = _oracle(s, 16).pcg(g, tol=1e-12)
+    assert np.linalg.norm(lam.cpu().numpy() - lr) <= 1e-9 * np.linalg.norm(lr)
+    Gr = oracle.adjoint_scatter(s.row_ptr, s.col_idx, lam.cpu().numpy(), x.cpu().numpy())
+    assert np.allclose(dH.cpu().numpy(), Gr, rtol=1e-6, atol=1e-6 * np.abs(Gr).max())
+
+
+# --------------------------------------------------------- full-size case ---
+
+
+@pytest.mark.slow
+def test_large_cube_parity(dev):
+    from paper_2411_06224_amd import bcsr_spmv
+
+    _say("large cube 48^3 parity")
+    s = large_cube()
+    H = _H(s, dev)
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(3 * s.n)
+    y = bcsr_spmv(H, _t(x, dev)).cpu().numpy()
+    ref = oracle.spmv(s.row_ptr, s.col_idx, s.val, x)
+    assert np.all(np.abs(y - ref) <= 1e-14 * _absH_absx(s, x) + 1e-300)
+    P = _oracle(s, 16)
+    S = _solver(s, 16)
+    S.build(H)
+    r = rng.standard_normal(3 * s.n)
+    z = S.apply(_t(r, dev)).cpu().numpy()
+    zr = P.apply(r)
+    assert np.linalg.norm(z - zr) <= 1e-10 * np.linalg.norm(zr)
+    xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+    xg, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10)
+    assert np.linalg.norm(xg.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)

@@ -1,0 +1,142 @@
+"""Host-side checks of libmaspcg: it loads, exports every symbol the header
+declares, validates arguments, and its symbolic analysis (partition, slots,
+supernode hierarchy) matches the oracle bit for bit.  No GPU work is run."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import cube, small_cube
+
+from paper_2411_06224_amd import _lib
+from paper_2411_06224_amd.solver import MasPcg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "mas_pcg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b([a-z_][a-z0-9_]*)\s*\(", text)) - {"sizeof"})
+
+
+def test_library_exports_every_header_function():
+    L = _lib.load()
+    names = _header_functions()
+    assert set(names) == set(_lib.SYMBOLS)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert _lib.status_string(code) and _lib.status_string(code) != "unknown status"
+    assert _lib.status_string(42) == "unknown status"
+
+
+def test_create_rejects_bad_options():
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    for opts in ((0, 0, 0, 0), (41, 0, 0, 0), (16, 0, 7, 0), (16, 0, 0, 1), (16, 17, 0, 0)):
+        o = _lib.MasOptions(*opts)
+        assert L.mas_create(ctypes.byref(o), ctypes.byref(h)) == _lib.MAS_INVALID_ARG
+    assert L.mas_create(None, ctypes.byref(h)) == _lib.MAS_OK
+    assert L.mas_workspace_size(h) == 0
+    L.mas_destroy(h)
+
+
+def _analyze_rc(rp, ci, graph=None, N=16):
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    o = _lib.MasOptions(N, 0, 0, 0)
+    assert L.mas_create(ctypes.byref(o), ctypes.byref(h)) == 0
+    rp = np.ascontiguousarray(rp, np.int32)
+    ci = np.ascontiguousarray(ci, np.int32)
+    rc = L.mas_analyze(h, rp.size - 1, ci.size, rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p), None, None)
+    L.mas_destroy(h)
+    return rc
+
+
+def test_analyze_rejects_invalid_patterns():
+    s = cube(1)
+    rp, ci = s.row_ptr.copy(), s.col_idx.copy()
+    assert _analyze_rc(rp, ci) == _lib.MAS_OK
+    bad = ci.copy()
+    bad[1], bad[2] = bad[2], bad[1]  # unsorted row
+    assert _analyze_rc(rp, bad) == _lib.MAS_INVALID_ARG
+    bad = ci.copy()
+    bad[0] = s.n  # out of range
+    assert _analyze_rc(rp, bad) == _lib.MAS_INVALID_ARG
+    # drop the (0,1) block only: pattern becomes asymmetric
+    k = int(np.nonzero(ci[rp[0] : rp[1]] == 1)[0][0])
+    ci2 = np.delete(ci, k)
+    rp2 = rp.copy()
+    rp2[1:] -= 1
+    assert _analyze_rc(rp2, ci2) == _lib.MAS_INVALID_ARG
+    # drop a diagonal block
+    k = int(np.nonzero(ci[rp[3] : rp[4]] == 3)[0][0]) + rp[3]
+    ci3 = np.delete(ci, k)
+    rp3 = rp.copy()
+    rp3[4:] -= 1
+    assert _analyze_rc(rp3, ci3) == _lib.MAS_INVALID_ARG
+    assert _analyze_rc(np.zeros(1, np.int32), np.zeros(0, np.int32)) == _lib.MAS_INVALID_ARG
+
+
+def _compare_with_oracle(s, N, max_levels=0, use_graph=True):
+    graph = (s.gptr, s.gadj) if use_graph else None
+    lib = MasPcg(s.row_ptr, s.col_idx, graph=graph, domain_size=N, max_levels=max_levels)
+    inf = lib.info()
+    mp, rm, sn = lib.ordering()
+    if use_graph:
+        P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels, gptr=s.gptr, gadj=s.gadj)
+    else:
+        P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels)
+    omp, orm = P.maps()
+    assert inf["parts"] == P.parts and inf["slack"] == P.slack
+    assert np.array_equal(mp, omp)
+    assert np.array_equal(rm, orm)
+    assert inf["levels"] == P.levels
+    for l in range(P.levels):
+        assert inf["units"][l] == P.units(l)
+        assert inf["domains"][l] == P.domains(l)
+        assert np.array_equal(sn[l], P.sn(l))
+    lib.close()
+    return inf
+
+
+@pytest.mark.parametrize("N", [1, 2, 4, 7, 16, 21, 32, 40])
+def test_ordering_bit_exact_small_cube(N):
+    _compare_with_oracle(small_cube(), N)
+
+
+@pytest.mark.parametrize("ml", [1, 2, 3])
+def test_ordering_bit_exact_level_cap(ml):
+    inf = _compare_with_oracle(small_cube(), 16, max_levels=ml)
+    assert inf["levels"] <= ml
+
+
+def test_ordering_bit_exact_default_graph_and_random_systems():
+    _compare_with_oracle(cube(3), 4, use_graph=False)
+    for seed in range(4):
+        s = synth.random_spd_system(300, 700, seed=seed, local=12)
+        _compare_with_oracle(s, 8)
+        _compare_with_oracle(s, 16, use_graph=False)
+
+
+def test_ordering_bit_exact_contact_cube():
+    s = cube(6, E=1e6, nu=0.49, seed=21, n_contacts=60)
+    inf = _compare_with_oracle(s, 16)
+    assert inf["levels"] >= 2
+
+
+@pytest.mark.slow
+def test_ordering_bit_exact_large_cube():
+    from conftest import large_cube
+
+    inf = _compare_with_oracle(large_cube(), 16)
+    assert inf["n_rows"] == 117649 and inf["nnzb"] == 1526513
