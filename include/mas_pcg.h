@@ -213,11 +213,11 @@ int mas_get_timings(const mas_handle* h, double* ms4);
 int mas_set_kernel_timing(mas_handle* h, int enable);
 
 /* Totals since the last mas_set_kernel_timing: total_ms[8] and launches[8]
- * for the kernel slots [0] SpMV q = H p with p^T q, [1] x/r update with
+ * for the kernel slots [0] direction update and SpMV q = H p with p^T q, [1] x/r update with
  * ||r||^2 and restriction to level 1, [2] coarse-level MAS apply,
- * [3] level-0 MAS apply with prolongation and r^T z, [4] p = z + beta p,
- * [5] FP64 residual replacement, [6] permutation of H, [7] restriction
- * only.  Host arrays. */
+ * [3] level-0 MAS apply with prolongation and r^T z, [4] reserved (0; the
+ * direction update p = z + beta p runs inside [0]), [5] FP64 residual
+ * replacement, [6] permutation of H, [7] restriction only.  Host arrays. */
 int mas_get_kernel_timing(const mas_handle* h, double* total_ms, int32_t* launches);
 
 /* Short English description of a status code (static string). */

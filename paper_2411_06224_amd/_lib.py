@@ -4,7 +4,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmaspcg.so")
+# MASPCG_LIBRARY may name another build of the same library (e.g. a tuning variant).
+LIB_PATH = os.environ.get("MASPCG_LIBRARY") or os.path.join(_HERE, "libmaspcg.so")
 
 MAS_OK = 0
 MAS_NOT_CONVERGED = 1

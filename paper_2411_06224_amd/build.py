@@ -36,25 +36,25 @@ def _run(cmd):
     return r.stdout
 
 
-def build(jobs=5):
+def build(jobs=5, csrc=CSRC, out_dir=OUT, lib=LIB, extra_flags=()):
     """Compile every source and link libmaspcg.so; always rebuilds."""
-    os.makedirs(OUT, exist_ok=True)
+    os.makedirs(out_dir, exist_ok=True)
     cmds = []
     objs = []
     for f in HIP_SOURCES:
-        o = os.path.join(OUT, f + ".o")
-        cmds.append([HIPCC, *DEVICE_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, f), "-o", o])
+        o = os.path.join(out_dir, f + ".o")
+        cmds.append([HIPCC, *DEVICE_FLAGS, *extra_flags, "-x", "hip", "-c", os.path.join(csrc, f), "-o", o])
         objs.append(o)
     for f in HOST_SOURCES:
-        o = os.path.join(OUT, f + ".o")
-        cmds.append(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f), "-o", o])
+        o = os.path.join(out_dir, f + ".o")
+        cmds.append(["g++", *HOST_FLAGS, "-c", os.path.join(csrc, f), "-o", o])
         objs.append(o)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(_run, cmds))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lamdhip64"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

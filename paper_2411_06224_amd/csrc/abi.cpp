@@ -21,11 +21,11 @@ constexpr size_t kAlign = 256;
 
 struct Layout {
     size_t total = 0;
-    size_t remap, map, perm_src, rp0, ci0, lead1, anc;
+    size_t remap, map, perm_src, rp0, ci0, lead1, anc, g_u1;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
-    size_t mem_ptr[kMaxLv], mem_idx[kMaxLv];
+    size_t anc1[kMaxLv], lead_pos[kMaxLv], cp_ptr[kMaxLv];
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
-    size_t b, x, r, z, p, q, r1, y[kMaxLv], partials, st, flag;
+    size_t b, x, r, z, p0, p1, q, r1, y[kMaxLv], cpart, P_sigma, P_rr, P_bb, P_rho0, P_rho1, st, flag;
     size_t inverse_bytes = 0;
 
     size_t take(size_t bytes) {
@@ -134,6 +134,7 @@ void make_layout(mas_handle* h) {
     Y.ci0 = Y.take(I * P.nnzb);
     Y.lead1 = Y.take(I * P.NS);
     Y.anc = Y.take(I * P.anc.size());
+    Y.g_u1 = Y.take(I * P.g_u1.size());
     for (int l = 0; l < P.L; ++l) {
         if (l >= 1) {
             Y.red_ptr[l] = Y.take(I * P.red_ptr[l].size());
@@ -143,8 +144,9 @@ void make_layout(mas_handle* h) {
         Y.dom_blk[l] = Y.take(I * P.dom_blk[l].size());
         Y.dom_ab[l] = Y.take(I * P.dom_ab[l].size());
         if (l >= 2) {
-            Y.mem_ptr[l] = Y.take(I * P.mem_ptr[l].size());
-            Y.mem_idx[l] = Y.take(I * P.mem_idx[l].size());
+            Y.anc1[l] = Y.take(I * P.anc1[l].size());
+            Y.lead_pos[l] = Y.take(I * P.lead_pos[l].size());
+            Y.cp_ptr[l] = Y.take(I * P.cp_ptr[l].size());
         }
     }
     Y.H64 = Y.take(Dd * 9 * P.nnzb);
@@ -156,17 +158,23 @@ void make_layout(mas_handle* h) {
         Y.inverse_bytes += (mixed ? F : Dd) * cnt;
         if (mixed) Y.inv32[l] = Y.take(F * cnt);
     }
-    const size_t vec = Dd * 3 * P.NS;
+    // slot vectors padded to whole groups so group kernels never branch on the tail
+    const size_t vec = Dd * 3 * static_cast<size_t>(P.G) * P.RG;
     Y.b = Y.take(vec);
     Y.x = Y.take(vec);
     Y.r = Y.take(vec);
     Y.z = Y.take(vec);
-    Y.p = Y.take(vec);
+    Y.p0 = Y.take(vec);
+    Y.p1 = Y.take(vec);
     Y.q = Y.take(vec);
     Y.r1 = Y.take(Dd * 3 * (P.L > 1 ? P.units[1] : 1));
     for (int l = 1; l < P.L; ++l) Y.y[l] = Y.take(Dd * 3 * static_cast<size_t>(P.ndom[l]) * P.N);
-    const int g = std::max({grid_spmv_rows(P.NS), grid_update(P.M, P.N), grid_apply0(P.M, P.N), 1024});
-    Y.partials = Y.take(Dd * 2 * g);
+    Y.cpart = Y.take(Dd * 3 * std::max(P.n_cpart, 1));
+    Y.P_sigma = Y.take(Dd * P.G);
+    Y.P_rr = Y.take(Dd * P.G);
+    Y.P_bb = Y.take(Dd * P.G);
+    Y.P_rho0 = Y.take(Dd * P.G);
+    Y.P_rho1 = Y.take(Dd * P.G);
     Y.st = Y.take(sizeof(DevState));
     Y.flag = Y.take(I);
 }
@@ -181,17 +189,28 @@ SolverView view(const mas_handle* h) {
     v.NS = P.NS;
     v.L = P.L;
     v.nnzb = P.nnzb;
+    v.D0 = P.D0;
+    v.RG = P.RG;
+    v.G = P.G;
     for (int l = 0; l < P.L; ++l) {
         v.units[l] = P.units[l];
         v.ndom[l] = P.ndom[l];
         v.inv64[l] = at<double>(h, Y.inv64[l]);
         v.inv32[l] = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.inv32[l]) : nullptr;
         if (l >= 2) {
-            v.mem_ptr[l] = at<int>(h, Y.mem_ptr[l]);
-            v.mem_idx[l] = at<int>(h, Y.mem_idx[l]);
+            v.anc1[l] = at<int>(h, Y.anc1[l]);
+            v.lead_pos[l] = at<int>(h, Y.lead_pos[l]);
+            v.cp_ptr[l] = at<int>(h, Y.cp_ptr[l]);
         }
         if (l >= 1) v.y[l] = at<double>(h, Y.y[l]);
     }
+    v.g_u1 = at<int>(h, Y.g_u1);
+    v.cpart = at<double>(h, Y.cpart);
+    v.P_sigma = at<double>(h, Y.P_sigma);
+    v.P_rr = at<double>(h, Y.P_rr);
+    v.P_bb = at<double>(h, Y.P_bb);
+    v.P_rho[0] = at<double>(h, Y.P_rho0);
+    v.P_rho[1] = at<double>(h, Y.P_rho1);
     v.remap = at<int>(h, Y.remap);
     v.map = at<int>(h, Y.map);
     v.perm_src = at<int>(h, Y.perm_src);
@@ -205,10 +224,10 @@ SolverView view(const mas_handle* h) {
     v.x = at<double>(h, Y.x);
     v.r = at<double>(h, Y.r);
     v.z = at<double>(h, Y.z);
-    v.p = at<double>(h, Y.p);
+    v.p[0] = at<double>(h, Y.p0);
+    v.p[1] = at<double>(h, Y.p1);
     v.q = at<double>(h, Y.q);
     v.r1 = at<double>(h, Y.r1);
-    v.partials = at<double>(h, Y.partials);
     v.st = at<DevState>(h, Y.st);
     v.flag = at<int>(h, Y.flag);
     return v;
@@ -255,6 +274,7 @@ int upload_plan(mas_handle* h, hipStream_t s) {
     HIP_TRY(put(Y.ci0, P.ci0));
     HIP_TRY(put(Y.lead1, P.lead1));
     HIP_TRY(put(Y.anc, P.anc));
+    HIP_TRY(put(Y.g_u1, P.g_u1));
     for (int l = 0; l < P.L; ++l) {
         if (l >= 1) {
             HIP_TRY(put(Y.red_ptr[l], P.red_ptr[l]));
@@ -264,8 +284,9 @@ int upload_plan(mas_handle* h, hipStream_t s) {
         HIP_TRY(put(Y.dom_blk[l], l == 0 ? h->translated[1] : P.dom_blk[l]));
         HIP_TRY(put(Y.dom_ab[l], P.dom_ab[l]));
         if (l >= 2) {
-            HIP_TRY(put(Y.mem_ptr[l], P.mem_ptr[l]));
-            HIP_TRY(put(Y.mem_idx[l], P.mem_idx[l]));
+            HIP_TRY(put(Y.anc1[l], P.anc1[l]));
+            HIP_TRY(put(Y.lead_pos[l], P.lead_pos[l]));
+            HIP_TRY(put(Y.cp_ptr[l], P.cp_ptr[l]));
         }
     }
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors are pageable
@@ -284,24 +305,13 @@ int finish_status(const DevState& st) {
     return MAS_NOT_CONVERGED;
 }
 
-hipError_t restrict_r(mas_handle* h, const SolverView& v, bool mixed, hipStream_t s) {
-    if (v.L < 2) return hipSuccess;
-    return timed(h, kKRestrict, s, [&] { return launch_update(v, true, mixed, s); });
-}
-
-hipError_t apply_init(mas_handle* h, const SolverView& v, bool mixed, hipStream_t s) {
+hipError_t apply_iter(mas_handle* h, const SolverView& v, bool mixed, int k, bool rr_true, hipStream_t s) {
     hipError_t e;
-    if ((e = restrict_r(h, v, mixed, s)) != hipSuccess) return e;
-    if ((e = launch_apply_coarse(v, mixed, kApplyInit, s)) != hipSuccess) return e;
-    return launch_apply_level0(v, mixed, kApplyInit, s);
-}
-
-hipError_t finish_iteration(mas_handle* h, const SolverView& v, bool mixed, hipStream_t s) {
-    hipError_t e;
-    if ((e = timed(h, kKCoarse, s, [&] { return launch_apply_coarse(v, mixed, kApplyIter, s); })) != hipSuccess) return e;
-    if ((e = timed(h, kKLevel0, s, [&] { return launch_apply_level0(v, mixed, kApplyIter, s); })) != hipSuccess)
+    if ((e = timed(h, kKCoarse, s, [&] {
+             return launch_apply_coarse(v, mixed, kApplyIter, k, 0.0, false, mixed, rr_true, s);
+         })) != hipSuccess)
         return e;
-    return timed(h, kKUpdateP, s, [&] { return launch_update_p(v, false, s); });
+    return timed(h, kKLevel0, s, [&] { return launch_apply_level0(v, mixed, kApplyIter, k, s); });
 }
 
 int read_state(mas_handle* h, const SolverView& v, hipStream_t s) {
@@ -311,7 +321,13 @@ int read_state(mas_handle* h, const SolverView& v, hipStream_t s) {
     return MAS_OK;
 }
 
-// The PCG driver shared by pcg_solve and pcg_adjoint.
+// The PCG driver shared by pcg_solve and pcg_adjoint.  Iteration k:
+//   p = z + beta p and q = H p (sigma partials) -> alpha, x += alpha p,
+//   r -= alpha q (||r||^2 partials, restriction) -> [mixed: FP64 residual
+//   replacement] -> convergence test and coarse apply -> level-0 apply and
+//   prolongation (rho partials).
+// The host reads the state every check_every iterations; iterations queued
+// after a stop return at once.
 int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, const pcg_options* o, pcg_result* res,
                hipStream_t s) {
     if (!h || !h->analyzed) return MAS_NOT_READY;
@@ -323,6 +339,7 @@ int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, con
     if (opt.replace_every <= 0) opt.replace_every = 50;
     if (opt.check_every <= 0) opt.check_every = 8;
     const bool mixed = h->opts.precision == MAS_PRECISION_MIXED;
+    const bool x0 = opt.x0_given != 0;
     const SolverView v = view(h);
 
     HIP_TRY(hipEventRecord(h->ev[kEvSolve0], s));
@@ -330,48 +347,51 @@ int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, con
     HIP_TRY(hipEventRecord(h->ev[kEvSolve1], s));
     HIP_TRY(launch_state_reset(v, s));
     HIP_TRY(launch_perm_in(v, b, v.b, s));
-    if (opt.x0_given) {
+    if (x0) {
         HIP_TRY(launch_perm_in(v, x, v.x, s));
-        HIP_TRY(launch_residual(v, kResidInit, opt.tol, v.r, s));
+        HIP_TRY(launch_residual(v, kResidInit, v.r, s));
     } else {
-        HIP_TRY(launch_init_rhs(v, opt.tol, s));
+        HIP_TRY(launch_init_rhs(v, s));
     }
-    HIP_TRY(apply_init(h, v, mixed, s));
-    HIP_TRY(launch_update_p(v, true, s));  // p = z
+    HIP_TRY(launch_apply_coarse(v, mixed, kApplyInit, 0, opt.tol, x0, mixed, false, s));
+    HIP_TRY(launch_apply_level0(v, mixed, kApplyInit, 0, s));
 
-    int enq = 0;
+    int k = 0;
     int rc = MAS_OK;
     DevState& st = *h->st_host;
     for (;;) {
-        const int nb = std::min(opt.check_every, opt.max_iter - enq);
+        const int nb = std::min(opt.check_every, opt.max_iter - k);
         for (int i = 0; i < nb; ++i) {
-            const int k = enq + i + 1;
-            HIP_TRY(timed(h, kKSpmv, s, [&] { return launch_spmv_pq(v, mixed, s); }));
-            HIP_TRY(timed(h, kKUpdate, s, [&] { return launch_update(v, false, mixed, s); }));
+            ++k;
+            HIP_TRY(timed(h, kKSpmv, s, [&] { return launch_spmv_pq(v, mixed, k, s); }));
+            HIP_TRY(timed(h, kKUpdate, s, [&] { return launch_update(v, k, s); }));
+            bool replaced = false;
             if (mixed && k % opt.replace_every == 0) {
-                HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidPeriodic, opt.tol, v.r, s); }));
-                HIP_TRY(restrict_r(h, v, mixed, s));
+                HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidReplace, v.r, s); }));
+                replaced = true;
             }
-            HIP_TRY(finish_iteration(h, v, mixed, s));
+            HIP_TRY(apply_iter(h, v, mixed, k, replaced, s));
         }
-        enq += nb;
         if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
         if (st.status < 0) break;
         if (st.done) {
             if (st.status != kStatusConvergedRecurrence) break;
-            // confirm on the FP64 residual b - H x (also a residual replacement)
-            HIP_TRY(launch_residual(v, kResidConfirm, opt.tol, v.r, s));
+            // stopped on the recurrence: confirm on the FP64 residual b - H x,
+            // which also replaces r; if it is not small enough, finish
+            // iteration st.iter with it and go on
+            k = st.iter;
+            HIP_TRY(launch_clear_stop(v, s));
+            HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidConfirm, v.r, s); }));
+            HIP_TRY(apply_iter(h, v, mixed, k, true, s));
             if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
             if (st.done || st.status < 0) break;
-            enq = st.iter;
-            HIP_TRY(restrict_r(h, v, mixed, s));
-            HIP_TRY(finish_iteration(h, v, mixed, s));
         }
-        if (enq >= opt.max_iter) break;
+        if (k >= opt.max_iter) break;
     }
     if (st.bb == 0.0)  // b = 0: the solution is x = b = 0 (also when an x0 was given)
         HIP_TRY(hipMemcpyAsync(v.x, v.b, sizeof(double) * 3 * v.NS, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_residual(v, kResidFinal, opt.tol, v.q, s));
+    HIP_TRY(launch_residual(v, kResidFinal, v.q, s));
+    HIP_TRY(launch_finalize(v, s));
     HIP_TRY(launch_perm_out(v, v.x, x, s));
     HIP_TRY(hipEventRecord(h->ev[kEvSolve2], s));
     if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
@@ -498,9 +518,9 @@ int mas_apply(mas_handle* h, const double* r, double* z, void* stream) {
     const SolverView v = view(h);
     const bool mixed = h->opts.precision == MAS_PRECISION_MIXED;
     HIP_TRY(launch_perm_in(v, r, v.r, s));
-    if (v.L > 1) HIP_TRY(launch_update(v, true, mixed, s));
-    HIP_TRY(launch_apply_coarse(v, mixed, kApplyPlain, s));
-    HIP_TRY(launch_apply_level0(v, mixed, kApplyPlain, s));
+    HIP_TRY(timed(h, kKRestrict, s, [&] { return launch_restrict(v, s); }));
+    HIP_TRY(launch_apply_coarse(v, mixed, kApplyPlain, 0, 0.0, false, mixed, false, s));
+    HIP_TRY(launch_apply_level0(v, mixed, kApplyPlain, 0, s));
     HIP_TRY(launch_perm_out(v, v.z, z, s));
     return MAS_OK;
 }

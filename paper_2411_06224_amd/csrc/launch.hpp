@@ -14,6 +14,7 @@ constexpr int kMaxLv = 16;
 // Device views of the solver's data in the caller's workspace.
 struct SolverView {
     int V, N, M, NS, L, nnzb;
+    int D0, RG, G;  // work groups: D0 level-0 domains = RG slots; G groups
     int units[kMaxLv];
     int ndom[kMaxLv];
     // plans
@@ -24,8 +25,10 @@ struct SolverView {
     const int* ci0;       // [nnzb]
     const int* lead1;     // [NS]
     const int* anc;       // [(L-1)*NS]
-    const int* mem_ptr[kMaxLv];
-    const int* mem_idx[kMaxLv];
+    const int* g_u1;      // [G+1]
+    const int* anc1[kMaxLv];      // l >= 2: [S_1]
+    const int* lead_pos[kMaxLv];  // l >= 2: [S_1]
+    const int* cp_ptr[kMaxLv];    // l >= 2: [S_l + 1]
     // slot-ordered matrix (9 planes of nnzb values)
     double* H64;
     float* H32;
@@ -33,13 +36,16 @@ struct SolverView {
     double* inv64[kMaxLv];
     float* inv32[kMaxLv];
     // vectors in slot order (3*NS doubles)
-    double *b, *x, *r, *z, *p, *q;
-    // coarse vectors: r1 [3*units[1]], y_l [3*ndom[l]*N] for l >= 1
+    double *b, *x, *r, *z, *q;
+    double* p[2];  // search direction p_k lives in p[k & 1]
+    // coarse vectors: r1 [3*units[1]], y_l [3*ndom[l]*N] for l >= 1, coarse partials [3*n_cpart]
     double* r1;
     double* y[kMaxLv];
-    double* partials;  // 2 * max grid
+    double* cpart;
+    // per-group partial sums [G] each
+    double *P_sigma, *P_rr, *P_bb, *P_rho[2];
     DevState* st;
-    int* flag;         // inversion status
+    int* flag;  // inversion status
 };
 
 // Build-phase views.
@@ -54,42 +60,50 @@ struct BuildView {
     const int* dom_blk[kMaxLv];  // level 0: caller block indices
     const int* dom_ab[kMaxLv];
     const int* remap;
-    double* A[kMaxLv];           // level l >= 1: 9 planes of nnzA[l]
+    double* A[kMaxLv];  // level l >= 1: 9 planes of nnzA[l]
     double* inv64[kMaxLv];
     float* inv32[kMaxLv];
     int* flag;
 };
 
-enum ResidMode { kResidInit = 0, kResidPeriodic = 1, kResidConfirm = 2, kResidFinal = 3 };
+// Residual kernel modes.
+enum ResidMode {
+    kResidInit = 0,     // r = b - H x0 with ||r||^2, ||b||^2 and the restriction
+    kResidReplace = 1,  // r = b - H x with ||r||^2 and the restriction (skipped after a stop)
+    kResidConfirm = 2,  // as kResidReplace, run after the host cleared a stop
+    kResidFinal = 3     // scratch = b - H x with ||.||^2 only
+};
+// Level-0 apply modes.
 enum ApplyMode { kApplyPlain = 0, kApplyInit = 1, kApplyIter = 2 };
 
 // spmv.hip
 hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void* val, bool f32, const double* x,
                             double* y, hipStream_t s);
-hipError_t launch_spmv_pq(const SolverView& v, bool f32, hipStream_t s);
-hipError_t launch_residual(const SolverView& v, int mode, double tol, double* out, hipStream_t s);
+// iteration k: p_k = z_{k-1} + beta p_{k-1} (p_1 = z_0) into p[k & 1], q = H p_k, sigma partials
+hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s);
+hipError_t launch_residual(const SolverView& v, int mode, double* out, hipStream_t s);
 
 // vectors.hip
 hipError_t launch_state_reset(const SolverView& v, hipStream_t s);
+hipError_t launch_clear_stop(const SolverView& v, hipStream_t s);
+hipError_t launch_finalize(const SolverView& v, hipStream_t s);
 hipError_t launch_permute_H(const SolverView& v, const double* Hu, bool f32, hipStream_t s);
 hipError_t launch_perm_in(const SolverView& v, const double* src, double* dst, hipStream_t s);
 hipError_t launch_perm_out(const SolverView& v, const double* src, double* dst, hipStream_t s);
-hipError_t launch_init_rhs(const SolverView& v, double tol, hipStream_t s);
-hipError_t launch_update(const SolverView& v, bool restrict_only, bool mixed, hipStream_t s);
-hipError_t launch_update_p(const SolverView& v, bool first, hipStream_t s);
+hipError_t launch_init_rhs(const SolverView& v, hipStream_t s);
+hipError_t launch_update(const SolverView& v, int k, hipStream_t s);
+hipError_t launch_restrict(const SolverView& v, hipStream_t s);
 hipError_t launch_adjoint_scatter(int n_rows, const int* rp, const int* ci, const double* lam, const double* x,
                                   void* out, bool f32, hipStream_t s);
 
 // mas.hip
 hipError_t launch_coarse_sums(const BuildView& b, const double* Hu, hipStream_t s);
 hipError_t launch_invert(const BuildView& b, const double* Hu, bool want32, hipStream_t s);
-hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, hipStream_t s);
-hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, hipStream_t s);
-
-// grid sizes (used for the partials buffer)
-int grid_spmv_rows(int rows);
-int grid_update(int M, int N);
-int grid_apply0(int M, int N);
-int grid_vector(int n);
+// Coarse levels plus the convergence decision of iteration k (k = 0: the
+// initial apply); rr_true: the residual partials hold b - H x rather than the
+// recurrence (residual replacement, FP64 confirmation).
+hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, int k, double tol, bool x0_given, bool mixed,
+                               bool rr_true, hipStream_t s);
+hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, hipStream_t s);
 
 }  // namespace maspcg

@@ -1,6 +1,8 @@
 // MAS preconditioner on the device: coarse matrices, batched domain
 // inversion and the apply (Supp. Eq. 4-6; algorithm "Compute MAS
 // preconditioner" in Sec. 3.3).
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace maspcg {
@@ -226,35 +228,87 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
 }
 
 // ------------------------------------------------------------------ apply
-// Coarse levels l >= 1 (one workgroup per domain, all levels in one launch):
-// r_l for the domain's N units (level 1 straight from r_1, higher levels as
-// sums over the level-1 supernodes below each unit, one wave per unit),
-// then y_l = Inv_{l,d} r_l.
+constexpr int kFlagX0 = 1, kFlagMixed = 2, kFlagRrTrue = 4;
 
-template <typename TI>
-__global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab, int check_done) {
+// Workgroup 0 of the coarse launch takes the convergence decision of the
+// iteration: it sums the ||r||^2 partials (and ||b||^2 for the first
+// apply) and records rr, the iteration count and, when ||r|| <= tol ||b||,
+// the stop for the host and every later kernel.  In mixed precision a stop
+// on the recurrence is marked for confirmation on the FP64 residual.
+__device__ void convergence_decision(const SolverView& v, int mode, int k, double tol, int flags, double* buf) {
+    DevState* st = v.st;
+    if (st->done) return;
+    const double rr = sum_partials(v.P_rr, v.G, buf);
+    if (mode == kApplyInit) {
+        const double bb = sum_partials(v.P_bb, v.G, buf);
+        const double tol2 = tol * tol * bb;
+        const bool bad = !finite(bb) || !finite(rr);
+        const bool stop = bad || bb == 0.0 || ((flags & kFlagX0) && rr <= tol2);
+        if (threadIdx.x == 0) {
+            st->bb = bb;
+            st->tol2 = tol2;
+            st->rr = rr;
+            st->iter = 0;
+            if (stop) {
+                st->status = bad ? -6 : 0;
+                st->done = 1;
+            }
+        }
+    } else {
+        const bool bad = !finite(rr);
+        const bool conv = rr <= st->tol2;
+        if (threadIdx.x == 0) {
+            st->rr = rr;
+            st->iter = k;
+            if (bad || conv) {
+                st->status = bad ? -6 : (((flags & kFlagMixed) && !(flags & kFlagRrTrue)) ? kStatusConvergedRecurrence : 0);
+                st->done = 1;
+            }
+        }
+    }
+}
+
+// Coarse levels l >= 1 (workgroups 1.. of the launch, one per domain, all
+// levels at once): r_l for the domain's N units -- level 1 straight from
+// r_1, higher levels as sums of the per-group partials the restriction left
+// for each unit (a contiguous range per unit, one wave per unit) -- then
+// y_l = Inv_{l,d} r_l.
+template <typename TI, int kN>
+__global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab, int mode, int k, double tol,
+                                                      int flags) {
     __shared__ double rl[128];
-    if (check_done && v.st->done) return;
+    __shared__ double buf[256];
+    if (blockIdx.x == 0) {
+        if (mode != kApplyPlain) convergence_decision(v, mode, k, tol, flags, buf);
+        return;
+    }
+    if (mode == kApplyIter && v.st->done) return;
+    const int gb = blockIdx.x - 1;
     int l = 1;
-    while (l + 1 < v.L && blockIdx.x >= tab.off[l + 1]) ++l;
-    const int d = blockIdx.x - tab.off[l];
-    const int N = v.N, n = 3 * N;
+    while (l + 1 < v.L && gb >= tab.off[l + 1]) ++l;
+    const int d = gb - tab.off[l];
+    const int N = kN > 0 ? kN : v.N, n = 3 * N;
     const int u0 = d * N;
     const int nu = min(N, v.units[l] - u0);
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     if (l == 1) {
         if (t < n) rl[t] = t < 3 * nu ? v.r1[3 * u0 + t] : 0.0;
     } else {
-        const int* mp = v.mem_ptr[l];
-        const int* mi = v.mem_idx[l];
+        const int* cp = v.cp_ptr[l];
         for (int a = w; a < N; a += 4) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
             if (a < nu) {
-                for (int m = mp[u0 + a] + lane; m < mp[u0 + a + 1]; m += 64) {
-                    const int k = mi[m];
-                    s0 += v.r1[3 * k];
-                    s1 += v.r1[3 * k + 1];
-                    s2 += v.r1[3 * k + 2];
+                const int m0 = cp[u0 + a], m1 = cp[u0 + a + 1];
+                for (int m = m0 + lane; m < m1; m += 128) {
+                    const int mb = m + 64;  // two independent loads in flight per lane
+                    s0 += v.cpart[3 * m];
+                    s1 += v.cpart[3 * m + 1];
+                    s2 += v.cpart[3 * m + 2];
+                    if (mb < m1) {
+                        s0 += v.cpart[3 * mb];
+                        s1 += v.cpart[3 * mb + 1];
+                        s2 += v.cpart[3 * mb + 2];
+                    }
                 }
             }
             s0 = wave_sum(s0);
@@ -274,72 +328,67 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
             inv = v.inv64[l];
         else
             inv = v.inv32[l];
-        inv += (long long)d * n * n;
+        inv += (long long)d * n * n + t;
         double acc = 0.0;
+        if constexpr (kN > 0) {
+#pragma unroll
+            for (int kk = 0; kk < 3 * kN; ++kk) acc += static_cast<double>(inv[kk * 3 * kN]) * rl[kk];
+        } else {
 #pragma unroll 8
-        for (int k = 0; k < n; ++k) acc += static_cast<double>(inv[k * n + t]) * rl[k];
+            for (int kk = 0; kk < n; ++kk) acc += static_cast<double>(inv[kk * n]) * rl[kk];
+        }
         v.y[l][3 * u0 + t] = acc;
     }
 }
 
-// Level 0: z = Inv_{0,d} r_d + sum_{l >= 1} y_l[unit of the slot at level l]
-// (prolongation of every coarse level, Supp. Eq. 6), with r^T z.  One wave
-// per domain when 3N <= 64, two otherwise.
-template <typename TI, int kMode>
-__global__ void __launch_bounds__(256) k_apply_level0(SolverView v) {
-    __shared__ double rs[4][64];
-    __shared__ double scratch[4];
+// Level 0 over a group of D0 domains, one thread per DOF:
+//   z = Inv_{0,d} r_d + sum_{l >= 1} y_l[unit of the slot at level l]
+// (prolongation of every coarse level, Supp. Eq. 6) and the partial of
+// rho = r^T z.  Returns at once after a stop.
+template <typename TI, int kN, int kMode>
+__global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
+    __shared__ double rs[384];
+    __shared__ double red[8];
+    const int N = kN > 0 ? kN : v.N;
+    const int n = 3 * N;
+    const int g = blockIdx.x, t = threadIdx.x;
     if (kMode != kApplyPlain && v.st->done) return;
-    const int N = v.N, n = 3 * N;
-    const int W = n > 64 ? 2 : 1;  // waves per domain
-    const int per = 4 / W;         // domains per workgroup
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int slot_in_wg = w / W;
-    const int tl = (w % W) * 64 + lane;  // row of the domain this lane computes
-    const int d = blockIdx.x * per + slot_in_wg;
-    const bool live = d < v.M && tl < n;
-    double* rsd = &rs[0][0] + slot_in_wg * 64 * W;
-    const long long base = 3LL * N * d;
-    double rv = 0.0;
-    if (live) {
-        rv = v.r[base + tl];
-        rsd[tl] = rv;
-    }
+    const int nd = min(v.D0, v.M - g * v.D0);  // domains of this group
+    const bool live = t < nd * n;
+    const long long base = 3LL * g * v.RG;
+    const double rv = live ? v.r[base + t] : 0.0;
+    if (t < 384) rs[t] = rv;
     __syncthreads();
     double zv = 0.0;
     if (live) {
+        const int dl = t / n, row = t - dl * n;
+        const int d = g * v.D0 + dl;
         const TI* inv;
         if constexpr (sizeof(TI) == 8)
             inv = v.inv64[0];
         else
             inv = v.inv32[0];
-        inv += (long long)d * n * n;
+        inv += (long long)d * n * n + row;
+        const double* rd = rs + dl * n;
         double acc = 0.0;
+        if constexpr (kN > 0) {
+#pragma unroll
+            for (int kk = 0; kk < 3 * kN; ++kk) acc += static_cast<double>(inv[kk * 3 * kN]) * rd[kk];
+        } else {
 #pragma unroll 8
-        for (int k = 0; k < n; ++k) acc += static_cast<double>(inv[k * n + tl]) * rsd[k];
-        const int slot = d * N + tl / 3, c = tl % 3;
+            for (int kk = 0; kk < n; ++kk) acc += static_cast<double>(inv[kk * n]) * rd[kk];
+        }
+        const int slot = g * v.RG + t / 3, c = t % 3;
         for (int l = 1; l < v.L; ++l) {
             const int u = v.anc[(long long)(l - 1) * v.NS + slot];
             if (u >= 0) acc += v.y[l][3 * u + c];
         }
         zv = acc;
-        v.z[base + tl] = zv;
+        v.z[base + t] = zv;
     }
     if (kMode == kApplyPlain) return;
-    double in[1] = {rv * zv}, out[1];
-    if (grid_reduce<1>(in, v.partials, &v.st->counter[kCntApply], out, scratch) && threadIdx.x == 0) {
-        DevState* st = v.st;
-        if (!finite(out[0])) {
-            st->status = -6;
-            st->done = 1;
-        } else if (kMode == kApplyInit) {
-            st->rho = out[0];
-            st->beta = 0.0;
-        } else {
-            st->beta = out[0] / st->rho;
-            st->rho = out[0];
-        }
-    }
+    const double part = block_sum(rv * zv, red);
+    if (t == 0) v.P_rho[k & 1][g] = part;
 }
 
 DomTable make_table(const int* ndom, int first, int L) {
@@ -360,8 +409,6 @@ void launch_invert_t(const BuildView& b, const double* Hu, bool want32, int tota
 }
 
 }  // namespace
-
-int grid_apply0(int M, int N) { return ceil_div(M, 3 * N > 64 ? 2 : 4); }
 
 hipError_t launch_coarse_sums(const BuildView& b, const double* Hu, hipStream_t s) {
     for (int l = 1; l < b.L; ++l) {
@@ -397,28 +444,39 @@ hipError_t launch_invert(const BuildView& b, const double* Hu, bool want32, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, hipStream_t s) {
-    if (v.L < 2) return hipSuccess;
+hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, int k, double tol, bool x0_given, bool mixed,
+                               bool rr_true, hipStream_t s) {
     const DomTable tab = make_table(v.ndom, 1, v.L);
-    const int total = tab.off[kMaxLv];
-    const int check = mode == kApplyPlain ? 0 : 1;
-    if (f32)
-        hipLaunchKernelGGL(k_apply_coarse<float>, dim3(total), dim3(256), 0, s, v, tab, check);
-    else
-        hipLaunchKernelGGL(k_apply_coarse<double>, dim3(total), dim3(256), 0, s, v, tab, check);
+    const int total = 1 + tab.off[kMaxLv];  // workgroup 0 decides convergence
+    const int flags = (x0_given ? kFlagX0 : 0) | (mixed ? kFlagMixed : 0) | (rr_true ? kFlagRrTrue : 0);
+    if (v.N == 16) {
+        if (f32) hipLaunchKernelGGL((k_apply_coarse<float, 16>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+        else hipLaunchKernelGGL((k_apply_coarse<double, 16>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_apply_coarse<float, 0>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+        else hipLaunchKernelGGL((k_apply_coarse<double, 0>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, hipStream_t s) {
-    dim3 g(grid_apply0(v.M, v.N)), b(256);
-    if (f32) {
-        if (mode == kApplyPlain) hipLaunchKernelGGL((k_apply_level0<float, kApplyPlain>), g, b, 0, s, v);
-        else if (mode == kApplyInit) hipLaunchKernelGGL((k_apply_level0<float, kApplyInit>), g, b, 0, s, v);
-        else hipLaunchKernelGGL((k_apply_level0<float, kApplyIter>), g, b, 0, s, v);
+template <typename TI, int kN>
+void launch_level0_t(const SolverView& v, int mode, int k, hipStream_t s) {
+    dim3 g(v.G), b(round_waves(3 * v.RG));
+    if (mode == kApplyPlain)
+        hipLaunchKernelGGL((k_apply_level0<TI, kN, kApplyPlain>), g, b, 0, s, v, k);
+    else if (mode == kApplyInit)
+        hipLaunchKernelGGL((k_apply_level0<TI, kN, kApplyInit>), g, b, 0, s, v, k);
+    else
+        hipLaunchKernelGGL((k_apply_level0<TI, kN, kApplyIter>), g, b, 0, s, v, k);
+}
+
+hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, hipStream_t s) {
+    if (v.N == 16) {
+        if (f32) launch_level0_t<float, 16>(v, mode, k, s);
+        else launch_level0_t<double, 16>(v, mode, k, s);
     } else {
-        if (mode == kApplyPlain) hipLaunchKernelGGL((k_apply_level0<double, kApplyPlain>), g, b, 0, s, v);
-        else if (mode == kApplyInit) hipLaunchKernelGGL((k_apply_level0<double, kApplyInit>), g, b, 0, s, v);
-        else hipLaunchKernelGGL((k_apply_level0<double, kApplyIter>), g, b, 0, s, v);
+        if (f32) launch_level0_t<float, 0>(v, mode, k, s);
+        else launch_level0_t<double, 0>(v, mode, k, s);
     }
     return hipGetLastError();
 }

@@ -22,6 +22,7 @@
 #include "planner.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <numeric>
 
@@ -369,21 +370,47 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
             const int below = l == 1 ? s : P.anc[static_cast<size_t>(l - 2) * P.NS + s];
             P.anc[static_cast<size_t>(l - 1) * P.NS + s] = below < 0 ? -1 : P.up[l - 1][below];
         }
-    P.mem_ptr.resize(P.L);
-    P.mem_idx.resize(P.L);
+    // ---- work groups and per-group coarse partials
+    P.D0 = std::max(1, 128 / N);
+    P.RG = P.D0 * N;
+    P.G = (P.M + P.D0 - 1) / P.D0;
+    P.g_u1.assign(P.G + 1, 0);
+    if (P.L > 1) {
+        // level-1 ids follow domain order: count the units of each group
+        for (int s = 0; s < P.NS; ++s)
+            if (P.lead1[s] >= 0) P.g_u1[s / P.RG + 1]++;
+        for (int g = 0; g < P.G; ++g) P.g_u1[g + 1] += P.g_u1[g];
+    }
+    P.anc1.assign(P.L, {});
+    P.lead_pos.assign(P.L, {});
+    P.cp_ptr.assign(P.L, {});
+    P.n_cpart = 0;
     if (P.L > 2) {
-        std::vector<int> a(P.units[1]);
+        const int S1 = P.units[1];
+        std::vector<int> a(S1);
         std::iota(a.begin(), a.end(), 0);
         for (int l = 2; l < P.L; ++l) {
             for (int& v : a) v = P.up[l - 1][v];
-            std::vector<int>& ptr = P.mem_ptr[l];
-            std::vector<int>& idx = P.mem_idx[l];
-            ptr.assign(P.units[l] + 1, 0);
-            for (int v : a) ptr[v + 1]++;
-            for (int u = 0; u < P.units[l]; ++u) ptr[u + 1] += ptr[u];
-            idx.resize(P.units[1]);
-            std::vector<int> fill(ptr.begin(), ptr.end() - 1);
-            for (int t = 0; t < P.units[1]; ++t) idx[fill[a[t]]++] = t;
+            P.anc1[l] = a;
+            // (unit, group, writer) of every distinct (group, unit) pair
+            std::vector<std::array<int, 3>> pairs;
+            std::vector<int> seen(P.units[l], -1);
+            for (int g = 0; g < P.G; ++g)
+                for (int t = P.g_u1[g]; t < P.g_u1[g + 1]; ++t)
+                    if (seen[a[t]] != g) {
+                        seen[a[t]] = g;
+                        pairs.push_back({a[t], g, t});
+                    }
+            std::sort(pairs.begin(), pairs.end());
+            P.lead_pos[l].assign(S1, -1);
+            P.cp_ptr[l].assign(P.units[l] + 1, 0);
+            for (size_t k = 0; k < pairs.size(); ++k) {
+                P.lead_pos[l][pairs[k][2]] = P.n_cpart + static_cast<int>(k);
+                P.cp_ptr[l][pairs[k][0] + 1]++;
+            }
+            P.cp_ptr[l][0] = P.n_cpart;
+            for (int u = 0; u < P.units[l]; ++u) P.cp_ptr[l][u + 1] += P.cp_ptr[l][u];
+            P.n_cpart += static_cast<int>(pairs.size());
         }
     }
 

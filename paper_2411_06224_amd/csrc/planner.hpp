@@ -43,8 +43,21 @@ struct Plan {
     // Restriction to level 1, per slot: the level-1 unit if this slot is the
     // lowest lane of that unit in its domain (it sums the unit), else -1.
     std::vector<int> lead1;
-    // Coarse restriction for l >= 2: level-l unit -> level-1 units below it.
-    std::vector<std::vector<int>> mem_ptr, mem_idx;
+
+    // Work groups of the vector kernels: D0 consecutive level-0 domains
+    // (RG = D0 * N slots); G groups.  Every reduction produces one partial
+    // per group.
+    int D0 = 0, RG = 0, G = 0;
+    std::vector<int> g_u1;  // [G+1] first level-1 unit of each group
+    // Coarse restriction for l >= 2 through per-group partial sums: the
+    // level-1 units of a group are summed per level-l ancestor; the partial
+    // of (group, ancestor) is written by the lowest such level-1 unit of the
+    // group to position lead_pos[l][t] (-1: not a writer).  The partials of
+    // level-l unit u occupy [cp_ptr[l][u], cp_ptr[l][u+1]) of one array.
+    std::vector<std::vector<int>> anc1;      // [l][S_1]: level-l unit of each level-1 unit
+    std::vector<std::vector<int>> lead_pos;  // [l][S_1]
+    std::vector<std::vector<int>> cp_ptr;    // [l][S_l + 1]
+    int n_cpart = 0;                         // partial positions over all levels
     // Prolongation: unit of every slot at levels 1..L-1, [(l-1) * NS + slot], -1 = empty.
     std::vector<int> anc;
 

@@ -1,0 +1,100 @@
+// Restriction of a residual to the coarse levels (C_l r of Supp. Eq. 6),
+// computed by the workgroup that owns a group of level-0 domains.
+//
+// restrict_prefetch() issues every plan load of the group at once (no
+// barrier), so its latency overlaps whatever the kernel does next;
+// restrict_group() then works from shared memory only.
+#pragma once
+
+#include "launch.hpp"
+
+namespace maspcg {
+
+// Shared memory of the restriction, in doubles, for a group of RG slots and
+// L levels: r1s[3 RG] doubles + up0[RG], lead[RG], anc[(L-2) RG], pos[(L-2) RG] ints.
+__host__ __device__ inline int restrict_smem_doubles(int RG, int L) {
+    const int ints = 2 * RG + 2 * (L > 2 ? L - 2 : 0) * RG;
+    return 3 * RG + (ints + 1) / 2;
+}
+
+struct RestrictSmem {
+    double* r1s;
+    int *up0, *lead, *anc, *pos;
+};
+
+__device__ inline RestrictSmem restrict_layout(const SolverView& v, double* sm) {
+    RestrictSmem r;
+    r.r1s = sm;
+    r.up0 = reinterpret_cast<int*>(sm + 3 * v.RG);
+    r.lead = r.up0 + v.RG;
+    r.anc = r.lead + v.RG;
+    r.pos = r.anc + (v.L > 2 ? v.L - 2 : 0) * v.RG;
+    return r;
+}
+
+// Loads the group's plan (level-1 unit and writer flag of every slot, and
+// for every level l >= 2 the ancestor and writer position of every level-1
+// unit of the group) into shared memory.  Needs a barrier before use.
+__device__ inline void restrict_prefetch(const SolverView& v, int g, double* sm) {
+    if (v.L < 2) return;
+    const RestrictSmem S = restrict_layout(v, sm);
+    const int RG = v.RG, slot0 = g * RG;
+    for (int i = threadIdx.x; i < RG; i += blockDim.x) {
+        const int slot = slot0 + i;
+        const bool in = slot < v.NS;
+        S.up0[i] = in ? v.anc[slot] : -1;
+        S.lead[i] = in ? v.lead1[slot] : -1;
+    }
+    if (v.L > 2) {
+        const int u1_lo = v.g_u1[g], n1 = v.g_u1[g + 1] - u1_lo;
+        const int tot = (v.L - 2) * n1;
+        for (int o = threadIdx.x; o < tot; o += blockDim.x) {
+            const int l = 2 + o / n1, i = o - (l - 2) * n1;
+            S.anc[(l - 2) * RG + i] = v.anc1[l][u1_lo + i];
+            S.pos[(l - 2) * RG + i] = v.lead_pos[l][u1_lo + i];
+        }
+    }
+}
+
+// rs[3*RG]: the group's residual in slot order (zero on slots >= NS), and
+// the prefetched plan, both visible to the workgroup (barrier done by the
+// caller).  Writes r_1 for the level-1 supernodes of the group (each summed
+// by its lowest slot, lanes in ascending order) and, for every level l >= 2,
+// one partial sum per (group, level-l supernode) at the position the plan
+// assigns (summed over the group's level-1 supernodes below it, ascending).
+// No atomics: every output has exactly one writer.
+__device__ inline void restrict_group(const SolverView& v, int g, const double* rs, double* sm) {
+    if (v.L < 2) return;
+    const RestrictSmem S = restrict_layout(v, sm);
+    const int RG = v.RG, N = v.N;
+    const int u1_lo = v.g_u1[g], n1 = v.g_u1[g + 1] - u1_lo;
+    for (int o = threadIdx.x; o < 3 * RG; o += blockDim.x) {
+        const int ls = o / 3, c = o - 3 * ls;
+        const int u = S.lead[ls];
+        if (u < 0) continue;
+        const int first = (ls / N) * N;
+        double s = 0.0;
+        for (int a = 0; a < N; ++a)
+            if (S.up0[first + a] == u) s += rs[3 * (first + a) + c];
+        v.r1[3 * u + c] = s;
+        S.r1s[3 * (u - u1_lo) + c] = s;
+    }
+    if (v.L > 2) {
+        __syncthreads();
+        const int tot = 3 * (v.L - 2) * n1;
+        for (int o = threadIdx.x; o < tot; o += blockDim.x) {
+            const int li = o / 3, c = o - 3 * li;
+            const int l = li / n1, i = li - l * n1;
+            const int pos = S.pos[l * RG + i];
+            if (pos < 0) continue;
+            const int* anc = S.anc + l * RG;
+            const int a = anc[i];
+            double s = 0.0;
+            for (int j = 0; j < n1; ++j)
+                if (anc[j] == a) s += S.r1s[3 * j + c];
+            v.cpart[3 * pos + c] = s;
+        }
+    }
+}
+
+}  // namespace maspcg

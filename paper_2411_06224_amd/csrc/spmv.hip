@@ -1,13 +1,25 @@
 // 3x3-block CSR sparse matrix-vector products (Supp. Eq. 2: T_spmv of a PCG
-// iteration).  A group of kSpmvLanes lanes owns one block row: lane k takes
-// blocks k, k + L, ... of the row, so the lanes of a group stream adjacent
-// blocks; the three row sums are then combined across the group with lane
-// shuffles in a fixed order.  Products are accumulated in FP64; FP32-stored
-// values are widened on load.
+// iteration).
+//
+// A workgroup owns a group of consecutive block rows and streams the
+// group's blocks, which are contiguous in memory, in chunks: thread t takes
+// blocks t, t + 256, ... of the chunk (consecutive threads read consecutive
+// values of each plane), multiplies each 3x3 block by its x entry and parks
+// the three products in LDS.  Every (row, component) pair of the group has
+// one owner thread that then adds its row's products in column order.  The
+// load is balanced by blocks, not rows, so rows of 7 and 19 blocks (the two
+// node classes of the tet cube) or long contact / affine rows cost the same
+// per block.  Products and sums are FP64; FP32-stored values are widened on
+// load.
 #include "launch.hpp"
+#include "restrict.hpp"
 
 namespace maspcg {
 namespace {
+
+constexpr int kThreads = 256;
+constexpr int kChunk = 1024;       // blocks staged in LDS per pass
+constexpr int kUserRows = 128;     // rows per workgroup for caller matrices
 
 // Block values: caller layout (9 consecutive values per block) or the
 // solver's planar layout (value c of block k at c * stride + k).
@@ -20,138 +32,170 @@ struct Blocks {
     }
 };
 
-// y(row) = sum_k H(row, k) x(col k), valid in lane 0 of the group.
-template <typename T, bool kPlanar>
-__device__ __forceinline__ void row_product(const int* __restrict__ rp, const int* __restrict__ ci, Blocks<T, kPlanar> H,
-                                            const double* __restrict__ x, int row, int sub, double& y0, double& y1,
-                                            double& y2) {
-    y0 = y1 = y2 = 0.0;
-    const int beg = rp[row], end = rp[row + 1];
-    for (int k = beg + sub; k < end; k += kSpmvLanes) {
-        const int j = ci[k];
-        const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
-        y0 += H.at(k, 0) * x0 + H.at(k, 1) * x1 + H.at(k, 2) * x2;
-        y1 += H.at(k, 3) * x0 + H.at(k, 4) * x1 + H.at(k, 5) * x2;
-        y2 += H.at(k, 6) * x0 + H.at(k, 7) * x1 + H.at(k, 8) * x2;
-    }
+// The vector H multiplies: x itself, or the new search direction
+// z + beta p formed on the fly from the previous one.
+struct XVec {
+    const double* __restrict__ x;
+    __device__ __forceinline__ double at(int i) const { return x[i]; }
+};
+struct XDir {
+    const double* __restrict__ z;
+    const double* __restrict__ p;
+    double beta;
+    __device__ __forceinline__ double at(int i) const { return __fma_rn(beta, p[i], z[i]); }
+};
+
+// Row sums of rows [r0, r1) of H x.  Owner o = 3 (row - r0) + c is thread
+// o (acc[0]) or o - 256 (acc[1]); 3 (r1 - r0) <= 512.  prod: 3 * kChunk LDS.
+template <typename T, bool kPlanar, typename X>
+__device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const int* __restrict__ ci,
+                                            Blocks<T, kPlanar> H, X x, int r0, int r1, double* prod,
+                                            double (&acc)[2]) {
+    const int t = threadIdx.x;
+    const int nown = 3 * (r1 - r0);
+    int rb[2], re[2];
 #pragma unroll
-    for (int o = kSpmvLanes / 2; o > 0; o >>= 1) {
-        y0 += __shfl_xor(y0, o, kSpmvLanes);
-        y1 += __shfl_xor(y1, o, kSpmvLanes);
-        y2 += __shfl_xor(y2, o, kSpmvLanes);
-    }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kSpmvThreads) k_spmv_user(int n_rows, const int* __restrict__ rp,
-                                                             const int* __restrict__ ci, const T* __restrict__ val,
-                                                             const double* __restrict__ x, double* __restrict__ y) {
-    const int row = blockIdx.x * kSpmvRows + threadIdx.x / kSpmvLanes;
-    const int sub = threadIdx.x % kSpmvLanes;
-    if (row >= n_rows) return;
-    double y0, y1, y2;
-    row_product<T, false>(rp, ci, Blocks<T, false>{val, 0}, x, row, sub, y0, y1, y2);
-    if (sub == 0) {
-        y[3 * row] = y0;
-        y[3 * row + 1] = y1;
-        y[3 * row + 2] = y2;
-    }
-}
-
-// PCG step q = H p with sigma = p^T q; the last workgroup forms
-// alpha = rho / sigma (or flags a breakdown when sigma <= 0).
-template <typename T>
-__global__ void __launch_bounds__(kSpmvThreads) k_spmv_pq(SolverView v, const T* __restrict__ H) {
-    __shared__ double scratch[kSpmvThreads / 64];
-    if (v.st->done) return;
-    const int row = blockIdx.x * kSpmvRows + threadIdx.x / kSpmvLanes;
-    const int sub = threadIdx.x % kSpmvLanes;
-    double part = 0.0;
-    if (row < v.NS) {
-        double y0, y1, y2;
-        row_product<T, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, v.p, row, sub, y0, y1, y2);
-        if (sub == 0) {
-            v.q[3 * row] = y0;
-            v.q[3 * row + 1] = y1;
-            v.q[3 * row + 2] = y2;
-            part = v.p[3 * row] * y0 + v.p[3 * row + 1] * y1 + v.p[3 * row + 2] * y2;
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        acc[q] = 0.0;
+        rb[q] = re[q] = 0;
+        if (o < nown) {
+            const int row = r0 + o / 3;
+            rb[q] = rp[row];
+            re[q] = rp[row + 1];
         }
     }
-    double in[1] = {part}, out[1];
-    if (grid_reduce<1>(in, v.partials, &v.st->counter[kCntSpmv], out, scratch) && threadIdx.x == 0) {
-        DevState* st = v.st;
-        const double sigma = out[0];
-        st->sigma = sigma;
-        if (!(sigma > 0.0) || !finite(sigma)) {
-            st->status = finite(sigma) ? -2 : -6;
-            st->done = 1;
-        } else {
-            st->alpha = st->rho / sigma;
+    const int kb = rp[r0], ke = rp[r1];
+    for (int cs = kb; cs < ke; cs += kChunk) {
+        const int ce = min(cs + kChunk, ke);
+#pragma unroll 4
+        for (int k = cs + t; k < ce; k += kThreads) {
+            const int j = ci[k];
+            const double x0 = x.at(3 * j), x1 = x.at(3 * j + 1), x2 = x.at(3 * j + 2);
+            const int e = k - cs;
+            prod[e] = H.at(k, 0) * x0 + H.at(k, 1) * x1 + H.at(k, 2) * x2;
+            prod[kChunk + e] = H.at(k, 3) * x0 + H.at(k, 4) * x1 + H.at(k, 5) * x2;
+            prod[2 * kChunk + e] = H.at(k, 6) * x0 + H.at(k, 7) * x1 + H.at(k, 8) * x2;
         }
-    }
-}
-
-// out = b - H x in FP64 (slot order), with ||out||^2 and ||b||^2.
-//  init:     out = r; sets rr, bb, tol2 and stops at once if b = 0 or x0 already converged
-//  periodic: out = r (residual replacement); skipped after a stop; a stop if converged
-//  confirm:  out = r; decides convergence on the FP64 residual (runs even after a stop)
-//  final:    out = scratch; records rr_true only
-template <int kMode>
-__global__ void __launch_bounds__(kSpmvThreads) k_residual(SolverView v, double tol, double* __restrict__ out) {
-    __shared__ double scratch[kSpmvThreads / 64];
-    if (kMode == kResidPeriodic && v.st->done) return;
-    const int row = blockIdx.x * kSpmvRows + threadIdx.x / kSpmvLanes;
-    const int sub = threadIdx.x % kSpmvLanes;
-    double rr = 0.0, bb = 0.0;
-    if (row < v.NS) {
-        double y0, y1, y2;
-        row_product<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, v.x, row, sub, y0, y1, y2);
-        if (sub == 0) {
-            const double e0 = v.b[3 * row] - y0, e1 = v.b[3 * row + 1] - y1, e2 = v.b[3 * row + 2] - y2;
-            out[3 * row] = e0;
-            out[3 * row + 1] = e1;
-            out[3 * row + 2] = e2;
-            rr = e0 * e0 + e1 * e1 + e2 * e2;
-            bb = v.b[3 * row] * v.b[3 * row] + v.b[3 * row + 1] * v.b[3 * row + 1] + v.b[3 * row + 2] * v.b[3 * row + 2];
-        }
-    }
-    double in[2] = {rr, bb}, tot[2];
-    if (grid_reduce<2>(in, v.partials, &v.st->counter[kCntResid], tot, scratch) && threadIdx.x == 0) {
-        DevState* st = v.st;
-        st->rr_true = tot[0];
-        if (kMode == kResidFinal) return;
-        st->rr = tot[0];
-        if (kMode == kResidInit) {
-            st->bb = tot[1];
-            st->tol2 = tol * tol * tot[1];
-            if (tot[1] == 0.0 || tot[0] <= st->tol2) st->done = 1;
-            if (!finite(tot[0]) || !finite(tot[1])) {
-                st->status = -6;
-                st->done = 1;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int o = t + q * kThreads;
+            if (o < nown) {
+                const int c = o % 3;
+                const int lo = max(rb[q], cs), hi = min(re[q], ce);
+                for (int k = lo; k < hi; ++k) acc[q] += prod[c * kChunk + (k - cs)];
             }
-            return;
         }
-        if (!finite(tot[0])) {
-            st->status = -6;
-            st->done = 1;
-        } else if (tot[0] <= st->tol2) {
-            st->status = 0;
-            st->done = 1;
-        } else if (kMode == kResidConfirm) {
-            st->status = 0;
-            st->done = 0;
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, const T* __restrict__ val,
+                                                         const double* __restrict__ x, double* __restrict__ y) {
+    __shared__ double prod[3 * kChunk];
+    const int r0 = blockIdx.x * kUserRows;
+    const int r1 = min(r0 + kUserRows, n_rows);
+    double acc[2];
+    stream_rows<T, false>(rp, ci, Blocks<T, false>{val, 0}, XVec{x}, r0, r1, prod, acc);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = threadIdx.x + q * kThreads;
+        if (o < 3 * (r1 - r0)) y[3 * r0 + o] = acc[q];
+    }
+}
+
+// PCG iteration k over the solver's group of slots: the new direction
+// p_k = z_{k-1} + beta_{k-1} p_{k-1} (beta = rho_{k-1} / rho_{k-2} summed from
+// the group partials; p_1 = z_0) is formed on the fly wherever H gathers it
+// and stored for the group's own rows; q = H p_k and the partial of p_k^T q.
+// Every workgroup forms the same beta and the same fused multiply-add, so a
+// direction entry has the same bits in every workgroup that reads it.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __restrict__ H, int k) {
+    __shared__ double prod[3 * kChunk];
+    __shared__ double buf[256];
+    if (v.st->done) return;
+    const int g = blockIdx.x;
+    const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
+    // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
+    const double rk1 = sum_partials(v.P_rho[(k - 1) & 1], v.G, buf);
+    if (g == 0 && threadIdx.x == 0) v.st->rho[(k - 1) & 1] = rk1;
+    double beta = 0.0;
+    const double* pold = v.z;  // k = 1: p_1 = z_0 (+ 0 * z_0)
+    if (k > 1) {
+        beta = rk1 / v.st->rho[k & 1];
+        pold = v.p[(k - 1) & 1];
+    }
+    const XDir dir{v.z, pold, beta};
+    double acc[2];
+    stream_rows<T, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, dir, r0, r1, prod, acc);
+    double* pk = v.p[k & 1];
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = threadIdx.x + q * kThreads;
+        if (o < 3 * (r1 - r0)) {
+            const long long i = 3LL * r0 + o;
+            const double pv = dir.at(i);
+            pk[i] = pv;
+            v.q[i] = acc[q];
+            part += pv * acc[q];
         }
     }
+    part = block_sum(part, buf);
+    if (threadIdx.x == 0) v.P_sigma[g] = part;
+}
+
+// out = b - H x in FP64 over a group, with the partials of ||out||^2 (and
+// ||b||^2 for the initial residual) and, except for the final check, the
+// restriction of the new residual to the coarse levels.
+template <int kMode>
+__global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __restrict__ out) {
+    __shared__ double prod[3 * kChunk];
+    __shared__ double scratch[kThreads / 64];
+    extern __shared__ double dyn[];  // rs[3*RG] + restriction scratch
+    if (kMode == kResidReplace && v.st->done) return;
+    const int g = blockIdx.x;
+    const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
+    double acc[2];
+    restrict_prefetch(v, g, dyn + 3 * v.RG);
+    stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, XVec{v.x}, r0, r1, prod, acc);
+    double rr = 0.0, bb = 0.0;
+    double* rs = dyn;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = threadIdx.x + q * kThreads;
+        if (o < 3 * v.RG) {
+            double e = 0.0;
+            if (o < 3 * (r1 - r0)) {
+                const long long i = 3LL * r0 + o;
+                const double bv = v.b[i];
+                e = bv - acc[q];
+                out[i] = e;
+                rr += e * e;
+                bb += bv * bv;
+            }
+            rs[o] = e;
+        }
+    }
+    rr = block_sum(rr, scratch);  // its barriers also publish rs
+    if (kMode == kResidInit) bb = block_sum(bb, scratch);
+    if (threadIdx.x == 0) {
+        v.P_rr[g] = rr;
+        if (kMode == kResidInit) v.P_bb[g] = bb;
+    }
+    if (kMode != kResidFinal) restrict_group(v, g, rs, dyn + 3 * v.RG);
 }
 
 }  // namespace
 
-int grid_spmv_rows(int rows) { return ceil_div(rows, kSpmvRows); }
-
 hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void* val, bool f32, const double* x,
                             double* y, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
-    dim3 g(grid_spmv_rows(n_rows)), b(kSpmvThreads);
+    dim3 g(ceil_div(n_rows, kUserRows)), b(kThreads);
     if (f32)
         hipLaunchKernelGGL(k_spmv_user<float>, g, b, 0, s, n_rows, rp, ci, static_cast<const float*>(val), x, y);
     else
@@ -159,22 +203,23 @@ hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_pq(const SolverView& v, bool f32, hipStream_t s) {
-    dim3 g(grid_spmv_rows(v.NS)), b(kSpmvThreads);
+hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s) {
+    dim3 g(v.G), b(kThreads);
     if (f32)
-        hipLaunchKernelGGL(k_spmv_pq<float>, g, b, 0, s, v, static_cast<const float*>(v.H32));
+        hipLaunchKernelGGL(k_spmv_pq<float>, g, b, 0, s, v, static_cast<const float*>(v.H32), k);
     else
-        hipLaunchKernelGGL(k_spmv_pq<double>, g, b, 0, s, v, static_cast<const double*>(v.H64));
+        hipLaunchKernelGGL(k_spmv_pq<double>, g, b, 0, s, v, static_cast<const double*>(v.H64), k);
     return hipGetLastError();
 }
 
-hipError_t launch_residual(const SolverView& v, int mode, double tol, double* out, hipStream_t s) {
-    dim3 g(grid_spmv_rows(v.NS)), b(kSpmvThreads);
+hipError_t launch_residual(const SolverView& v, int mode, double* out, hipStream_t s) {
+    dim3 g(v.G), b(kThreads);
+    const size_t shmem = sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.L));
     switch (mode) {
-        case kResidInit: hipLaunchKernelGGL(k_residual<kResidInit>, g, b, 0, s, v, tol, out); break;
-        case kResidPeriodic: hipLaunchKernelGGL(k_residual<kResidPeriodic>, g, b, 0, s, v, tol, out); break;
-        case kResidConfirm: hipLaunchKernelGGL(k_residual<kResidConfirm>, g, b, 0, s, v, tol, out); break;
-        default: hipLaunchKernelGGL(k_residual<kResidFinal>, g, b, 0, s, v, tol, out); break;
+        case kResidInit: hipLaunchKernelGGL(k_residual<kResidInit>, g, b, shmem, s, v, out); break;
+        case kResidReplace: hipLaunchKernelGGL(k_residual<kResidReplace>, g, b, shmem, s, v, out); break;
+        case kResidConfirm: hipLaunchKernelGGL(k_residual<kResidConfirm>, g, b, shmem, s, v, out); break;
+        default: hipLaunchKernelGGL(k_residual<kResidFinal>, g, b, shmem, s, v, out); break;
     }
     return hipGetLastError();
 }

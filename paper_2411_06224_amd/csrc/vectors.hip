@@ -1,20 +1,40 @@
 // Vector kernels of the PCG iteration (Supp. Eq. 2: T_dot and T_axpby), the
 // slot permutation of H and vectors, and the adjoint block scatter.
+//
+// The iteration kernels work on groups of D0 consecutive level-0 domains
+// (RG slots, one thread per DOF).  Every dot product leaves one partial per
+// group; the kernel that needs the scalar sums the partials itself in a
+// fixed order, so no kernel waits on other workgroups and no atomics are
+// used.
 #include "launch.hpp"
+#include "restrict.hpp"
 
 namespace maspcg {
 namespace {
 
 constexpr int kVecThreads = 256;
-constexpr int kInitGrid = 1024;
 
 __global__ void k_state_reset(DevState* st) {
     if (threadIdx.x == 0) {
-        st->rho = st->sigma = st->alpha = st->beta = 0.0;
         st->rr = st->bb = st->tol2 = st->rr_true = 0.0;
-        st->done = st->iter = st->status = st->check = 0;
-        for (int k = 0; k < 8; ++k) st->counter[k] = 0u;
+        st->rho[0] = st->rho[1] = 0.0;
+        st->done = st->iter = st->status = st->pad = 0;
     }
+}
+
+// Resumes the iteration after a stop that the host decided to revisit.
+__global__ void k_clear_stop(DevState* st) {
+    if (threadIdx.x == 0) {
+        st->done = 0;
+        st->status = 0;
+    }
+}
+
+// rr_true = sum of the residual partials (after the final residual kernel).
+__global__ void __launch_bounds__(256) k_finalize(SolverView v) {
+    __shared__ double buf[256];
+    const double rr = sum_partials(v.P_rr, v.G, buf);
+    if (threadIdx.x == 0) v.st->rr_true = rr;
 }
 
 // Caller-ordered FP64 blocks -> slot-ordered planar FP64 (and FP32) copies.
@@ -52,119 +72,108 @@ __global__ void __launch_bounds__(kVecThreads) k_perm_out(int V, const int* __re
     dst[t] = src[3 * map[t / 3] + t % 3];
 }
 
-// r = b, x = 0, ||b||^2; sets bb, rr, tol2 and stops at once when b = 0.
-__global__ void __launch_bounds__(kVecThreads) k_init_rhs(SolverView v, double tol) {
-    __shared__ double scratch[kVecThreads / 64];
-    const int n = 3 * v.NS;
-    double bb = 0.0;
-    for (int t = blockIdx.x * kVecThreads + threadIdx.x; t < n; t += gridDim.x * kVecThreads) {
-        const double bv = v.b[t];
-        v.r[t] = bv;
-        v.x[t] = 0.0;
-        bb += bv * bv;
-    }
-    double in[1] = {bb}, out[1];
-    if (grid_reduce<1>(in, v.partials, &v.st->counter[kCntInit], out, scratch) && threadIdx.x == 0) {
-        DevState* st = v.st;
-        st->bb = out[0];
-        st->rr = out[0];
-        st->rr_true = out[0];
-        st->tol2 = tol * tol * out[0];
-        if (out[0] == 0.0) st->done = 1;
-        if (!finite(out[0])) {
-            st->status = -6;
-            st->done = 1;
-        }
-    }
+// Shared memory of the group kernels: rs[3*RG] + restriction scratch + 256.
+inline size_t group_smem(const SolverView& v) {
+    return sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.L) + 256);
 }
 
-// Domains per workgroup of the domain-aligned vector kernels (3 * D * N <= 192 lanes in use).
-__host__ __device__ inline int update_domains(int N) { return N >= 64 ? 1 : (64 / N > 0 ? 64 / N : 1); }
-
-// x += alpha p, r -= alpha q, ||r||^2, and the restriction r_1 = C_1 r of the
-// updated residual: each level-1 supernode is summed by the lowest slot of
-// its level-0 domain that belongs to it (no atomics, fixed order).  With
-// kRestrictOnly the vectors are left unchanged and only r_1 is formed.
-template <bool kRestrictOnly>
-__global__ void k_update(SolverView v, int mixed) {
+// r = b, x = 0, partials of ||b||^2 (as both ||r||^2 and ||b||^2), and the
+// restriction of r.
+__global__ void k_init_rhs(SolverView v) {
     extern __shared__ double sm[];
-    const int D = update_domains(v.N);
-    const int slots = D * v.N;
-    double* rs = sm;                                    // [3 * slots]
-    int* up = reinterpret_cast<int*>(sm + 3 * slots);   // [slots]
-    double* scratch = sm + 3 * slots + (slots + 1) / 2; // [4]
-    if (!kRestrictOnly && v.st->done) return;
-    const int t = threadIdx.x;
-    const int ls = t / 3, c = t % 3;
-    const int slot = blockIdx.x * slots + ls;
-    const bool valid = ls < slots && slot < v.NS;
-    const int dof = 3 * slot + c;
-    double rv = 0.0;
-    if (valid) {
-        if (kRestrictOnly) {
-            rv = v.r[dof];
-        } else {
-            const double alpha = v.st->alpha;
-            v.x[dof] += alpha * v.p[dof];
-            rv = v.r[dof] - alpha * v.q[dof];
-            v.r[dof] = rv;
+    double* rs = sm;
+    double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.L);
+    const int g = blockIdx.x, t = threadIdx.x;
+    restrict_prefetch(v, g, sm + 3 * v.RG);
+    const long long i = 3LL * g * v.RG + t;
+    double bv = 0.0;
+    if (t < 3 * v.RG) {
+        if (i < 3LL * v.NS) {
+            bv = v.b[i];
+            v.r[i] = bv;
+            v.x[i] = 0.0;
         }
+        rs[t] = bv;
     }
-    if (v.L > 1) {
-        if (ls < slots) rs[t] = rv;
-        if (c == 0 && ls < slots) up[ls] = valid ? v.anc[slot] : -1;
-        __syncthreads();
-        if (valid) {
-            const int u = v.lead1[slot];
-            if (u >= 0) {
-                const int first = (ls / v.N) * v.N;
-                double s = 0.0;
-                for (int a = 0; a < v.N; ++a)
-                    if (up[first + a] == u) s += rs[3 * (first + a) + c];
-                v.r1[3 * u + c] = s;
-            }
-        }
+    const double bb = block_sum(bv * bv, scratch);
+    if (t == 0) {
+        v.P_rr[g] = bb;
+        v.P_bb[g] = bb;
     }
-    if (kRestrictOnly) return;
-    double in[1] = {rv * rv}, out[1];
-    if (grid_reduce<1>(in, v.partials, &v.st->counter[kCntUpdate], out, scratch) && threadIdx.x == 0) {
-        DevState* st = v.st;
-        st->rr = out[0];
-        st->iter += 1;
-        if (!finite(out[0])) {
-            st->status = -6;
-            st->done = 1;
-        } else if (out[0] <= st->tol2) {
-            st->status = mixed ? kStatusConvergedRecurrence : 0;
-            st->done = 1;
-        }
-    }
+    restrict_group(v, g, rs, sm + 3 * v.RG);
 }
 
-// p = z + beta p (first = 1: p = z, p holds no earlier direction)
-__global__ void __launch_bounds__(kVecThreads) k_update_p(SolverView v, int first) {
+// Iteration k: alpha = rho_{k-1} / sigma_k (sigma summed here from the group
+// partials, rho_{k-1} as the SpMV of this iteration recorded it), x += alpha p,
+// r -= alpha q, the partial of ||r||^2 and the restriction of the new
+// residual.  sigma <= 0 stops the solve (NOT_SPD).
+__global__ void k_update(SolverView v, int k) {
+    extern __shared__ double sm[];
+    double* rs = sm;
+    double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.L);
     if (v.st->done) return;
-    const int t = blockIdx.x * kVecThreads + threadIdx.x;
-    if (t >= 3 * v.NS) return;
-    if (first) {
-        v.p[t] = v.z[t];
-    } else {
-        const double beta = v.st->beta;
-        v.p[t] = v.z[t] + beta * v.p[t];
+    const int g = blockIdx.x, t = threadIdx.x;
+    // issue every independent load before the first barrier
+    restrict_prefetch(v, g, sm + 3 * v.RG);
+    const long long i = 3LL * g * v.RG + t;
+    const bool own = t < 3 * v.RG && i < 3LL * v.NS;
+    const double* pk = v.p[k & 1];
+    double xv = 0.0, pv = 0.0, rv0 = 0.0, qv = 0.0;
+    if (own) {
+        xv = v.x[i];
+        pv = pk[i];
+        rv0 = v.r[i];
+        qv = v.q[i];
     }
+    const double sigma = sum_partials(v.P_sigma, v.G, scratch);
+    const double rho = v.st->rho[(k - 1) & 1];
+    if (!(sigma > 0.0) || !finite(sigma) || !finite(rho)) {
+        if (g == 0 && t == 0) {
+            v.st->status = (finite(sigma) && finite(rho)) ? -2 : -6;
+            v.st->done = 1;
+            v.st->iter = k - 1;
+        }
+        return;
+    }
+    const double alpha = rho / sigma;
+    double rv = 0.0;
+    if (own) {
+        v.x[i] = xv + alpha * pv;
+        rv = rv0 - alpha * qv;
+        v.r[i] = rv;
+    }
+    if (t < 3 * v.RG) rs[t] = rv;
+    const double rr = block_sum(rv * rv, scratch);  // its barriers also publish rs and the plan
+    if (t == 0) v.P_rr[g] = rr;
+    restrict_group(v, g, rs, sm + 3 * v.RG);
+}
+
+// Restriction of the current r only (preconditioner apply outside PCG).
+__global__ void k_restrict(SolverView v) {
+    extern __shared__ double sm[];
+    double* rs = sm;
+    const int g = blockIdx.x, t = threadIdx.x;
+    restrict_prefetch(v, g, sm + 3 * v.RG);
+    const long long i = 3LL * g * v.RG + t;
+    if (t < 3 * v.RG) rs[t] = i < 3LL * v.NS ? v.r[i] : 0.0;
+    __syncthreads();
+    restrict_group(v, g, rs, sm + 3 * v.RG);
 }
 
 // dL/dH_ij = -lambda_i x_j^T on every stored block, caller order and layout.
+// Eight lanes per block row; consecutive lanes write consecutive blocks.
+constexpr int kScatterLanes = 8;
+
 template <typename T>
-__global__ void __launch_bounds__(kSpmvThreads) k_adjoint_scatter(int n_rows, const int* __restrict__ rp,
-                                                                   const int* __restrict__ ci,
-                                                                   const double* __restrict__ lam,
-                                                                   const double* __restrict__ x, T* __restrict__ out) {
-    const int row = blockIdx.x * kSpmvRows + threadIdx.x / kSpmvLanes;
-    const int sub = threadIdx.x % kSpmvLanes;
+__global__ void __launch_bounds__(kVecThreads) k_adjoint_scatter(int n_rows, const int* __restrict__ rp,
+                                                                  const int* __restrict__ ci,
+                                                                  const double* __restrict__ lam,
+                                                                  const double* __restrict__ x, T* __restrict__ out) {
+    const int row = blockIdx.x * (kVecThreads / kScatterLanes) + threadIdx.x / kScatterLanes;
+    const int sub = threadIdx.x % kScatterLanes;
     if (row >= n_rows) return;
     const double l0 = lam[3 * row], l1 = lam[3 * row + 1], l2 = lam[3 * row + 2];
-    for (int k = rp[row] + sub; k < rp[row + 1]; k += kSpmvLanes) {
+    for (int k = rp[row] + sub; k < rp[row + 1]; k += kScatterLanes) {
         const int j = ci[k];
         const double x0 = x[3 * j], x1 = x[3 * j + 1], x2 = x[3 * j + 2];
         T* o = out + 9LL * k;
@@ -180,61 +189,63 @@ __global__ void __launch_bounds__(kSpmvThreads) k_adjoint_scatter(int n_rows, co
     }
 }
 
-}  // namespace
+// Group kernels run whole waves and at least 256 threads (sum_partials).
+int group_threads(const SolverView& v) { return max(256, round_waves(3 * v.RG)); }
 
-int grid_update(int M, int N) { return ceil_div(M, update_domains(N)); }
-int grid_vector(int n) { return ceil_div(n, kVecThreads); }
+}  // namespace
 
 hipError_t launch_state_reset(const SolverView& v, hipStream_t s) {
     hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, v.st);
     return hipGetLastError();
 }
 
+hipError_t launch_clear_stop(const SolverView& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_stop, dim3(1), dim3(64), 0, s, v.st);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const SolverView& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_permute_H(const SolverView& v, const double* Hu, bool f32, hipStream_t s) {
-    hipLaunchKernelGGL(k_permute_H, dim3(grid_vector(v.nnzb)), dim3(kVecThreads), 0, s, v.nnzb, v.perm_src, Hu, v.H64,
-                       f32 ? v.H32 : nullptr);
+    hipLaunchKernelGGL(k_permute_H, dim3(ceil_div(v.nnzb, kVecThreads)), dim3(kVecThreads), 0, s, v.nnzb, v.perm_src, Hu,
+                       v.H64, f32 ? v.H32 : nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_perm_in(const SolverView& v, const double* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_in, dim3(grid_vector(3 * v.NS)), dim3(kVecThreads), 0, s, v.NS, v.remap, src, dst);
+    hipLaunchKernelGGL(k_perm_in, dim3(ceil_div(3LL * v.NS, kVecThreads)), dim3(kVecThreads), 0, s, v.NS, v.remap, src,
+                       dst);
     return hipGetLastError();
 }
 
 hipError_t launch_perm_out(const SolverView& v, const double* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_out, dim3(grid_vector(3 * v.V)), dim3(kVecThreads), 0, s, v.V, v.map, src, dst);
+    hipLaunchKernelGGL(k_perm_out, dim3(ceil_div(3LL * v.V, kVecThreads)), dim3(kVecThreads), 0, s, v.V, v.map, src, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_init_rhs(const SolverView& v, double tol, hipStream_t s) {
-    int g = grid_vector(3 * v.NS);
-    if (g > kInitGrid) g = kInitGrid;
-    hipLaunchKernelGGL(k_init_rhs, dim3(g), dim3(kVecThreads), 0, s, v, tol);
+hipError_t launch_init_rhs(const SolverView& v, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_rhs, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v);
     return hipGetLastError();
 }
 
-hipError_t launch_update(const SolverView& v, bool restrict_only, bool mixed, hipStream_t s) {
-    const int D = update_domains(v.N);
-    const int slots = D * v.N;
-    const int threads = (3 * slots + 63) / 64 * 64;  // whole waves: shuffle reductions need every lane live
-    const size_t shmem = sizeof(double) * (3 * slots + (slots + 1) / 2 + 4);
-    dim3 g(grid_update(v.M, v.N)), b(threads);
-    if (restrict_only)
-        hipLaunchKernelGGL(k_update<true>, g, b, shmem, s, v, mixed ? 1 : 0);
-    else
-        hipLaunchKernelGGL(k_update<false>, g, b, shmem, s, v, mixed ? 1 : 0);
+hipError_t launch_update(const SolverView& v, int k, hipStream_t s) {
+    hipLaunchKernelGGL(k_update, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v, k);
     return hipGetLastError();
 }
 
-hipError_t launch_update_p(const SolverView& v, bool first, hipStream_t s) {
-    hipLaunchKernelGGL(k_update_p, dim3(grid_vector(3 * v.NS)), dim3(kVecThreads), 0, s, v, first ? 1 : 0);
+hipError_t launch_restrict(const SolverView& v, hipStream_t s) {
+    if (v.L < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_scatter(int n_rows, const int* rp, const int* ci, const double* lam, const double* x,
                                   void* out, bool f32, hipStream_t s) {
     if (n_rows <= 0) return hipSuccess;
-    dim3 g(grid_spmv_rows(n_rows)), b(kSpmvThreads);
+    dim3 g(ceil_div(n_rows, kVecThreads / kScatterLanes)), b(kVecThreads);
     if (f32)
         hipLaunchKernelGGL(k_adjoint_scatter<float>, g, b, 0, s, n_rows, rp, ci, lam, x, static_cast<float*>(out));
     else
