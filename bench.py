@@ -24,6 +24,37 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 256 << 20  # calibration copy: bytes read (and written) per copy
+
+# Sources that define each hot kernel; HBM traffic measured with rocprofv3
+# counters (profiles/pmc_traffic.json) is used only while they are unchanged.
+KERNEL_SOURCES = {
+    "spmv": ["spmv.hip", "common.hpp", "launch.hpp", "restrict.hpp"],
+    "apply_level0": ["mas.hip", "common.hpp", "launch.hpp"],
+}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_2411_06224_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch (fetch + write) from the committed counter runs,
+    or None when there is none for this kernel or its sources changed since."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel)
+    if not rec or rec.get("source_sha256") != kernel_source_hash(kernel):
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def log(*a):
@@ -41,8 +72,9 @@ def algorithmic_bytes(info, mixed):
     inv = 4 if mixed else 8
     coarse_y = sum(8 * 3 * info["domains"][l] * N for l in range(1, L))
     out = {
-        # values + column index + row pointer, p read once, q written
-        "spmv": nnzb * (val + 4) + 4 * (NS + 1) + 2 * vb,
+        # values + column index + row pointer; z and the previous direction
+        # read once (the direction update is fused in), new direction and q written
+        "spmv": nnzb * (val + 4) + 4 * (NS + 1) + 4 * vb,
         # level-0 inverses, r read, z written, per-slot coarse ids, coarse corrections
         "apply_level0": info["domains"][0] * n * n * inv + 2 * vb + 4 * (L - 1) * NS + coarse_y,
         # coarse inverses, restricted residual read, y written
@@ -51,7 +83,6 @@ def algorithmic_bytes(info, mixed):
         + coarse_y,
         # x, r read+write, p, q read, per-slot plan ints, r_1 written
         "update": 6 * vb + 8 * NS + (8 * 3 * info["units"][1] if L > 1 else 0),
-        "update_p": 3 * vb,
     }
     return out
 
@@ -66,6 +97,11 @@ def main():
     ap.add_argument("--domain-size", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / adjoint / instrumented runs")
+    ap.add_argument(
+        "--calibrate-copy",
+        action="store_true",
+        help="first copy a 256 MiB buffer three times (a plain copy of known size for counter calibration)",
+    )
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -85,6 +121,13 @@ def main():
     mp.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     t0 = time.time()
     s = synth.config_large(E=args.E)
@@ -184,7 +227,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(dom),
             "alg_bytes_per_launch": nbytes[dom],
             "avg_launch_us": per[dom]["avg_us"],
         }

@@ -10,6 +10,18 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+// Inverse entries in the apply.  FP64 inverses (136 MB at the 48^3 cube) do
+// not fit the 256 MB MALL next to H, so they are streamed with non-temporal
+// loads that leave the caches to H and the vectors; the FP32 set of the mixed
+// solve fits and is read through the caches.
+template <typename TI>
+__device__ __forceinline__ double inv_load(const TI* p) {
+    if constexpr (sizeof(TI) == 8)
+        return __builtin_nontemporal_load(p);
+    else
+        return static_cast<double>(*p);
+}
+
 // ------------------------------------------------------------ coarse sums
 // A_l = C H C^T by levels (Supp. Eq. 5: A_(l) = C A C^T with unit 3x3
 // weights).  Each coarse block owns a list of fine blocks and sums it in a
@@ -332,10 +344,10 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
         double acc = 0.0;
         if constexpr (kN > 0) {
 #pragma unroll
-            for (int kk = 0; kk < 3 * kN; ++kk) acc += static_cast<double>(inv[kk * 3 * kN]) * rl[kk];
+            for (int kk = 0; kk < 3 * kN; ++kk) acc += inv_load(inv + kk * 3 * kN) * rl[kk];
         } else {
 #pragma unroll 8
-            for (int kk = 0; kk < n; ++kk) acc += static_cast<double>(inv[kk * n]) * rl[kk];
+            for (int kk = 0; kk < n; ++kk) acc += inv_load(inv + kk * n) * rl[kk];
         }
         v.y[l][3 * u0 + t] = acc;
     }
@@ -373,10 +385,10 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
         double acc = 0.0;
         if constexpr (kN > 0) {
 #pragma unroll
-            for (int kk = 0; kk < 3 * kN; ++kk) acc += static_cast<double>(inv[kk * 3 * kN]) * rd[kk];
+            for (int kk = 0; kk < 3 * kN; ++kk) acc += inv_load(inv + kk * 3 * kN) * rd[kk];
         } else {
 #pragma unroll 8
-            for (int kk = 0; kk < n; ++kk) acc += static_cast<double>(inv[kk * n]) * rd[kk];
+            for (int kk = 0; kk < n; ++kk) acc += inv_load(inv + kk * n) * rd[kk];
         }
         const int slot = g * v.RG + t / 3, c = t % 3;
         for (int l = 1; l < v.L; ++l) {
