@@ -206,10 +206,11 @@ int mas_get_ordering(const mas_handle* h, int32_t* map, int32_t* remap, int32_t*
 int mas_get_timings(const mas_handle* h, double* ms4);
 
 /* Per-launch kernel timing for measurement.  With enable != 0 every later
- * pcg_solve / pcg_adjoint brackets each launch of its iteration kernels with
- * a pair of HIP events on the call's stream and accumulates the elapsed
- * times (this adds event packets between launches, so leave it off for
- * timed runs).  Enabling or disabling clears the totals. */
+ * pcg_solve / pcg_adjoint launches its iteration kernels with a pair of HIP
+ * events that the runtime stamps with that dispatch's own start and end, and
+ * accumulates the elapsed times (the event bookkeeping adds host work per
+ * launch, so leave it off for timed runs).  Enabling or disabling clears the
+ * totals. */
 int mas_set_kernel_timing(mas_handle* h, int enable);
 
 /* Totals since the last mas_set_kernel_timing: total_ms[8] and launches[8]

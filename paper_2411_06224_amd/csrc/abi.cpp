@@ -76,10 +76,12 @@ namespace {
         if ((expr) != hipSuccess) return MAS_HIP_ERROR; \
     } while (0)
 
-// Runs one launch; with kernel timing on, brackets it with a pair of HIP
-// events on the same stream (resolved at the next synchronisation).
+// Runs one launch; with kernel timing on, hands it a pair of HIP events that
+// the runtime stamps with that dispatch's own start and end (resolved at the
+// next synchronisation).
 template <typename F>
 hipError_t timed(mas_handle* h, int slot, hipStream_t s, F&& launch) {
+    (void)s;
     KernelTimer& t = h->kt;
     if (!t.on) return launch();
     if (t.used + 2 > t.pool.size()) {
@@ -90,14 +92,16 @@ hipError_t timed(mas_handle* h, int slot, hipStream_t s, F&& launch) {
             t.pool.push_back(e);
         }
     }
-    hipError_t err = hipEventRecord(t.pool[t.used], s);
+    DispatchEvents& de = dispatch_events();
+    de = DispatchEvents{t.pool[t.used], t.pool[t.used + 1]};
+    const hipError_t err = launch();
+    const bool launched = de.start == nullptr;  // a launcher with nothing to do leaves them
+    de = DispatchEvents{};
     if (err != hipSuccess) return err;
-    err = launch();
-    if (err != hipSuccess) return err;
-    err = hipEventRecord(t.pool[t.used + 1], s);
-    if (err != hipSuccess) return err;
-    t.used += 2;
-    t.pending.push_back(slot);
+    if (launched) {
+        t.used += 2;
+        t.pending.push_back(slot);
+    }
     return hipSuccess;
 }
 

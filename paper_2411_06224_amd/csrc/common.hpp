@@ -25,6 +25,21 @@ struct DevState {
 
 constexpr int kStatusConvergedRecurrence = 2;
 
+// ------------------------------------------------------------ XCD placement
+
+// The dispatcher deals workgroups to the 8 XCDs round-robin (workgroup b runs
+// on XCD b % 8), each XCD behind its own L2.  Groups of slots that exchange
+// halo entries are numbered close together by the partition, so each XCD is
+// given one contiguous range of the G groups (a bijection of [0, G)) and
+// neighbouring groups share that XCD's L2.
+constexpr int kXcds = 8;
+
+__host__ __device__ inline int xcd_group(int b, int G) {
+    const int x = b % kXcds, i = b / kXcds;
+    const int q = G / kXcds, rem = G % kXcds;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
 // ---------------------------------------------------------------- reductions
 
 __device__ inline double wave_sum(double v) {

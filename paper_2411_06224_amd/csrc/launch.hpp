@@ -1,6 +1,7 @@
 // Host launchers of the HIP kernels and their argument blocks.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -10,6 +11,24 @@
 namespace maspcg {
 
 constexpr int kMaxLv = 16;
+
+// Kernel timing: when set, the next launch reports its own start and end to
+// these events (the runtime stamps them from the dispatch itself, so the
+// elapsed time excludes the gaps between launches); the launch consumes them.
+struct DispatchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+inline DispatchEvents& dispatch_events() {
+    static thread_local DispatchEvents e;
+    return e;
+}
+
+template <typename F, typename... Args>
+void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, Args... args) {
+    DispatchEvents& e = dispatch_events();
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e.start, e.stop, 0u, args...);
+    e = DispatchEvents{};
+}
 
 // Device views of the solver's data in the caller's workspace.
 struct SolverView {

@@ -363,7 +363,7 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
     __shared__ double red[8];
     const int N = kN > 0 ? kN : v.N;
     const int n = 3 * N;
-    const int g = blockIdx.x, t = threadIdx.x;
+    const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
     if (kMode != kApplyPlain && v.st->done) return;
     const int nd = min(v.D0, v.M - g * v.D0);  // domains of this group
     const bool live = t < nd * n;
@@ -417,7 +417,7 @@ DomTable make_table(const int* ndom, int first, int L) {
 
 template <int T>
 void launch_invert_t(const BuildView& b, const double* Hu, bool want32, int total, const DomTable& tab, hipStream_t s) {
-    hipLaunchKernelGGL(k_invert<T>, dim3(total), dim3(64), 0, s, b, Hu, want32 ? 1 : 0, tab);
+    launch_kernel(k_invert<T>, dim3(total), dim3(64), 0, s, b, Hu, want32 ? 1 : 0, tab);
 }
 
 }  // namespace
@@ -427,10 +427,10 @@ hipError_t launch_coarse_sums(const BuildView& b, const double* Hu, hipStream_t 
         const int g = ceil_div(b.nnzA[l], 256);
         if (g == 0) continue;
         if (l == 1)
-            hipLaunchKernelGGL(k_coarse_sum_first, dim3(g), dim3(256), 0, s, b.nnzA[1], b.red_ptr[1], b.red_src[1], Hu,
+            launch_kernel(k_coarse_sum_first, dim3(g), dim3(256), 0, s, b.nnzA[1], b.red_ptr[1], b.red_src[1], Hu,
                                b.A[1]);
         else
-            hipLaunchKernelGGL(k_coarse_sum_next, dim3(g), dim3(256), 0, s, b.nnzA[l], b.nnzA[l - 1], b.red_ptr[l],
+            launch_kernel(k_coarse_sum_next, dim3(g), dim3(256), 0, s, b.nnzA[l], b.nnzA[l - 1], b.red_ptr[l],
                                b.red_src[l], b.A[l - 1], b.A[l]);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -462,11 +462,11 @@ hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, int k, d
     const int total = 1 + tab.off[kMaxLv];  // workgroup 0 decides convergence
     const int flags = (x0_given ? kFlagX0 : 0) | (mixed ? kFlagMixed : 0) | (rr_true ? kFlagRrTrue : 0);
     if (v.N == 16) {
-        if (f32) hipLaunchKernelGGL((k_apply_coarse<float, 16>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
-        else hipLaunchKernelGGL((k_apply_coarse<double, 16>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+        if (f32) launch_kernel((k_apply_coarse<float, 16>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+        else launch_kernel((k_apply_coarse<double, 16>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
     } else {
-        if (f32) hipLaunchKernelGGL((k_apply_coarse<float, 0>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
-        else hipLaunchKernelGGL((k_apply_coarse<double, 0>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+        if (f32) launch_kernel((k_apply_coarse<float, 0>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
+        else launch_kernel((k_apply_coarse<double, 0>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
     }
     return hipGetLastError();
 }
@@ -475,11 +475,11 @@ template <typename TI, int kN>
 void launch_level0_t(const SolverView& v, int mode, int k, hipStream_t s) {
     dim3 g(v.G), b(round_waves(3 * v.RG));
     if (mode == kApplyPlain)
-        hipLaunchKernelGGL((k_apply_level0<TI, kN, kApplyPlain>), g, b, 0, s, v, k);
+        launch_kernel((k_apply_level0<TI, kN, kApplyPlain>), g, b, 0, s, v, k);
     else if (mode == kApplyInit)
-        hipLaunchKernelGGL((k_apply_level0<TI, kN, kApplyInit>), g, b, 0, s, v, k);
+        launch_kernel((k_apply_level0<TI, kN, kApplyInit>), g, b, 0, s, v, k);
     else
-        hipLaunchKernelGGL((k_apply_level0<TI, kN, kApplyIter>), g, b, 0, s, v, k);
+        launch_kernel((k_apply_level0<TI, kN, kApplyIter>), g, b, 0, s, v, k);
 }
 
 hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, hipStream_t s) {

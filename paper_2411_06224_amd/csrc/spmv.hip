@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     __shared__ double prod[3 * kChunk];
     __shared__ double buf[256];
     if (v.st->done) return;
-    const int g = blockIdx.x;
+    const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
     const double rk1 = sum_partials(v.P_rho[(k - 1) & 1], v.G, buf);
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
     __shared__ double scratch[kThreads / 64];
     extern __shared__ double dyn[];  // rs[3*RG] + restriction scratch
     if (kMode == kResidReplace && v.st->done) return;
-    const int g = blockIdx.x;
+    const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     double acc[2];
     restrict_prefetch(v, g, dyn + 3 * v.RG);
@@ -197,18 +197,18 @@ hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void
     if (n_rows <= 0) return hipSuccess;
     dim3 g(ceil_div(n_rows, kUserRows)), b(kThreads);
     if (f32)
-        hipLaunchKernelGGL(k_spmv_user<float>, g, b, 0, s, n_rows, rp, ci, static_cast<const float*>(val), x, y);
+        launch_kernel(k_spmv_user<float>, g, b, 0, s, n_rows, rp, ci, static_cast<const float*>(val), x, y);
     else
-        hipLaunchKernelGGL(k_spmv_user<double>, g, b, 0, s, n_rows, rp, ci, static_cast<const double*>(val), x, y);
+        launch_kernel(k_spmv_user<double>, g, b, 0, s, n_rows, rp, ci, static_cast<const double*>(val), x, y);
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s) {
     dim3 g(v.G), b(kThreads);
     if (f32)
-        hipLaunchKernelGGL(k_spmv_pq<float>, g, b, 0, s, v, static_cast<const float*>(v.H32), k);
+        launch_kernel(k_spmv_pq<float>, g, b, 0, s, v, static_cast<const float*>(v.H32), k);
     else
-        hipLaunchKernelGGL(k_spmv_pq<double>, g, b, 0, s, v, static_cast<const double*>(v.H64), k);
+        launch_kernel(k_spmv_pq<double>, g, b, 0, s, v, static_cast<const double*>(v.H64), k);
     return hipGetLastError();
 }
 
@@ -216,10 +216,10 @@ hipError_t launch_residual(const SolverView& v, int mode, double* out, hipStream
     dim3 g(v.G), b(kThreads);
     const size_t shmem = sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.L));
     switch (mode) {
-        case kResidInit: hipLaunchKernelGGL(k_residual<kResidInit>, g, b, shmem, s, v, out); break;
-        case kResidReplace: hipLaunchKernelGGL(k_residual<kResidReplace>, g, b, shmem, s, v, out); break;
-        case kResidConfirm: hipLaunchKernelGGL(k_residual<kResidConfirm>, g, b, shmem, s, v, out); break;
-        default: hipLaunchKernelGGL(k_residual<kResidFinal>, g, b, shmem, s, v, out); break;
+        case kResidInit: launch_kernel(k_residual<kResidInit>, g, b, shmem, s, v, out); break;
+        case kResidReplace: launch_kernel(k_residual<kResidReplace>, g, b, shmem, s, v, out); break;
+        case kResidConfirm: launch_kernel(k_residual<kResidConfirm>, g, b, shmem, s, v, out); break;
+        default: launch_kernel(k_residual<kResidFinal>, g, b, shmem, s, v, out); break;
     }
     return hipGetLastError();
 }

@@ -83,7 +83,7 @@ __global__ void k_init_rhs(SolverView v) {
     extern __shared__ double sm[];
     double* rs = sm;
     double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.L);
-    const int g = blockIdx.x, t = threadIdx.x;
+    const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
     restrict_prefetch(v, g, sm + 3 * v.RG);
     const long long i = 3LL * g * v.RG + t;
     double bv = 0.0;
@@ -112,7 +112,7 @@ __global__ void k_update(SolverView v, int k) {
     double* rs = sm;
     double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.L);
     if (v.st->done) return;
-    const int g = blockIdx.x, t = threadIdx.x;
+    const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
     // issue every independent load before the first barrier
     restrict_prefetch(v, g, sm + 3 * v.RG);
     const long long i = 3LL * g * v.RG + t;
@@ -152,7 +152,7 @@ __global__ void k_update(SolverView v, int k) {
 __global__ void k_restrict(SolverView v) {
     extern __shared__ double sm[];
     double* rs = sm;
-    const int g = blockIdx.x, t = threadIdx.x;
+    const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
     restrict_prefetch(v, g, sm + 3 * v.RG);
     const long long i = 3LL * g * v.RG + t;
     if (t < 3 * v.RG) rs[t] = i < 3LL * v.NS ? v.r[i] : 0.0;
@@ -195,50 +195,50 @@ int group_threads(const SolverView& v) { return max(256, round_waves(3 * v.RG));
 }  // namespace
 
 hipError_t launch_state_reset(const SolverView& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(64), 0, s, v.st);
+    launch_kernel(k_state_reset, dim3(1), dim3(64), 0, s, v.st);
     return hipGetLastError();
 }
 
 hipError_t launch_clear_stop(const SolverView& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_stop, dim3(1), dim3(64), 0, s, v.st);
+    launch_kernel(k_clear_stop, dim3(1), dim3(64), 0, s, v.st);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(const SolverView& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, v);
+    launch_kernel(k_finalize, dim3(1), dim3(256), 0, s, v);
     return hipGetLastError();
 }
 
 hipError_t launch_permute_H(const SolverView& v, const double* Hu, bool f32, hipStream_t s) {
-    hipLaunchKernelGGL(k_permute_H, dim3(ceil_div(v.nnzb, kVecThreads)), dim3(kVecThreads), 0, s, v.nnzb, v.perm_src, Hu,
+    launch_kernel(k_permute_H, dim3(ceil_div(v.nnzb, kVecThreads)), dim3(kVecThreads), 0, s, v.nnzb, v.perm_src, Hu,
                        v.H64, f32 ? v.H32 : nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_perm_in(const SolverView& v, const double* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_in, dim3(ceil_div(3LL * v.NS, kVecThreads)), dim3(kVecThreads), 0, s, v.NS, v.remap, src,
+    launch_kernel(k_perm_in, dim3(ceil_div(3LL * v.NS, kVecThreads)), dim3(kVecThreads), 0, s, v.NS, v.remap, src,
                        dst);
     return hipGetLastError();
 }
 
 hipError_t launch_perm_out(const SolverView& v, const double* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(k_perm_out, dim3(ceil_div(3LL * v.V, kVecThreads)), dim3(kVecThreads), 0, s, v.V, v.map, src, dst);
+    launch_kernel(k_perm_out, dim3(ceil_div(3LL * v.V, kVecThreads)), dim3(kVecThreads), 0, s, v.V, v.map, src, dst);
     return hipGetLastError();
 }
 
 hipError_t launch_init_rhs(const SolverView& v, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_rhs, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v);
+    launch_kernel(k_init_rhs, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v);
     return hipGetLastError();
 }
 
 hipError_t launch_update(const SolverView& v, int k, hipStream_t s) {
-    hipLaunchKernelGGL(k_update, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v, k);
+    launch_kernel(k_update, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v, k);
     return hipGetLastError();
 }
 
 hipError_t launch_restrict(const SolverView& v, hipStream_t s) {
     if (v.L < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v);
+    launch_kernel(k_restrict, dim3(v.G), dim3(group_threads(v)), group_smem(v), s, v);
     return hipGetLastError();
 }
 
@@ -247,9 +247,9 @@ hipError_t launch_adjoint_scatter(int n_rows, const int* rp, const int* ci, cons
     if (n_rows <= 0) return hipSuccess;
     dim3 g(ceil_div(n_rows, kVecThreads / kScatterLanes)), b(kVecThreads);
     if (f32)
-        hipLaunchKernelGGL(k_adjoint_scatter<float>, g, b, 0, s, n_rows, rp, ci, lam, x, static_cast<float*>(out));
+        launch_kernel(k_adjoint_scatter<float>, g, b, 0, s, n_rows, rp, ci, lam, x, static_cast<float*>(out));
     else
-        hipLaunchKernelGGL(k_adjoint_scatter<double>, g, b, 0, s, n_rows, rp, ci, lam, x, static_cast<double*>(out));
+        launch_kernel(k_adjoint_scatter<double>, g, b, 0, s, n_rows, rp, ci, lam, x, static_cast<double*>(out));
     return hipGetLastError();
 }
 
