@@ -52,7 +52,7 @@ def build(jobs=5, csrc=CSRC, out_dir=OUT, lib=LIB, extra_flags=()):
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(_run, cmds))
     tmp = lib + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lamdhip64"])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lamdhip64"])
     os.replace(tmp, lib)
     return lib
 

@@ -264,18 +264,53 @@ def test_pcg_deterministic(dev):
     assert torch.equal(x1, x2) and r1 == r2
 
 
+@pytest.mark.parametrize("max_iter", [1, 2, 7, 9, 17])
+def test_pcg_stop_at_every_iteration_count(dev, max_iter):
+    """Fixed iteration counts around the host check period (8): the iterate
+    after exactly max_iter iterations, whatever batch the stop falls in."""
+    _say("pcg max_iter", max_iter)
+    s = SYSTEMS["contact6"]()
+    xr, st, it, *_ = _oracle(s, 16).pcg(s.b, tol=0.0, max_iter=max_iter)
+    S = _solver(s, 16)
+    H = _H(s, dev)
+    S.build(H)
+    x, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=max_iter)
+    assert res["iterations"] == it == max_iter
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
+def test_pcg_long_range_couplings(dev):
+    """Random long-range couplings: every group touches thousands of columns
+    and the hierarchy runs to the level cap."""
+    _say("pcg wide random")
+    s = synth.random_spd_system(4000, 60000, seed=4)
+    P = _oracle(s, 16)
+    S = _solver(s, 16)
+    H = _H(s, dev)
+    S.build(H)
+    xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+    x, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10)
+    assert res["iterations"] == it == 10 and res["status"] == 1
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+    xr, st, it, *_ = P.pcg(s.b, tol=1e-8)
+    x, res = S.solve(H, _t(s.b, dev), tol=1e-8)
+    assert res["status"] == 0 and st == 0 and abs(res["iterations"] - it) <= 2
+    xv = x.cpu().numpy()
+    assert np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) <= 1.01e-8 * np.linalg.norm(s.b)
+
+
 # ----------------------------------------------------------------- mixed ---
 
 
-@pytest.mark.parametrize("tol", [1e-4, 1e-6])
-def test_mixed_precision_small(dev, tol):
-    _say("mixed", tol)
+@pytest.mark.parametrize("tol,replace_every", [(1e-4, 50), (1e-6, 50), (1e-6, 3), (1e-8, 7)])
+def test_mixed_precision_small(dev, tol, replace_every):
+    _say("mixed", tol, replace_every)
     s = small_cube()
     xr, *_ = _oracle(s, 16).pcg(s.b, tol=1e-12)
     S = _solver(s, 16, precision="mixed")
     H = _H(s, dev)
     S.build(H)
-    x, res = S.solve(H, _t(s.b, dev), tol=tol)
+    x, res = S.solve(H, _t(s.b, dev), tol=tol, replace_every=replace_every)
     assert res["status"] == 0
     xv = x.cpu().numpy()
     true = np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) / np.linalg.norm(s.b)
