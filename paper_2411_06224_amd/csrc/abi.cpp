@@ -23,7 +23,7 @@ struct Layout {
     size_t total = 0;
     size_t remap, map, perm_src, rp0, ci0, lead1, anc, g_u1;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
-    size_t anc1[kMaxLv], lead_pos[kMaxLv], cp_ptr[kMaxLv];
+    size_t ganc[kMaxLv], gpos[kMaxLv], cp_ptr[kMaxLv];
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
     size_t b, x, r, z, p0, p1, q, r1, y[kMaxLv], cpart, P_sigma, P_rr, P_bb, P_rho0, P_rho1, st, flag;
     size_t inverse_bytes = 0;
@@ -35,7 +35,7 @@ struct Layout {
     }
 };
 
-enum { kEvBuild0 = 0, kEvBuild1, kEvBuild2, kEvSolve0, kEvSolve1, kEvSolve2, kEvCount };
+enum { kEvBuild0 = 0, kEvBuild1, kEvBuild2, kEvSolve0, kEvSolve1, kEvSolve2, kEvPoll0, kEvPoll1, kEvCount };
 
 // Kernel slots of the optional per-launch timing (mas_set_kernel_timing).
 enum { kKSpmv = 0, kKUpdate, kKCoarse, kKLevel0, kKUpdateP, kKResidual, kKPermute, kKRestrict, kKSlots };
@@ -61,7 +61,7 @@ struct mas_handle {
     size_t ws_size = 0;
     char* uploaded_to = nullptr;
     bool built = false;
-    DevState* st_host = nullptr;  // pinned
+    DevState* st_host = nullptr;  // pinned: [0] last blocking read, [1..2] per-batch copies
     int* flag_host = nullptr;     // pinned
     hipEvent_t ev[kEvCount]{};
     bool events = false;
@@ -148,8 +148,8 @@ void make_layout(mas_handle* h) {
         Y.dom_blk[l] = Y.take(I * P.dom_blk[l].size());
         Y.dom_ab[l] = Y.take(I * P.dom_ab[l].size());
         if (l >= 2) {
-            Y.anc1[l] = Y.take(I * P.anc1[l].size());
-            Y.lead_pos[l] = Y.take(I * P.lead_pos[l].size());
+            Y.ganc[l] = Y.take(I * P.ganc[l].size());
+            Y.gpos[l] = Y.take(I * P.gpos[l].size());
             Y.cp_ptr[l] = Y.take(I * P.cp_ptr[l].size());
         }
     }
@@ -196,14 +196,15 @@ SolverView view(const mas_handle* h) {
     v.D0 = P.D0;
     v.RG = P.RG;
     v.G = P.G;
+    v.W1 = P.W1;
     for (int l = 0; l < P.L; ++l) {
         v.units[l] = P.units[l];
         v.ndom[l] = P.ndom[l];
         v.inv64[l] = at<double>(h, Y.inv64[l]);
         v.inv32[l] = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.inv32[l]) : nullptr;
         if (l >= 2) {
-            v.anc1[l] = at<int>(h, Y.anc1[l]);
-            v.lead_pos[l] = at<int>(h, Y.lead_pos[l]);
+            v.ganc[l] = at<int>(h, Y.ganc[l]);
+            v.gpos[l] = at<int>(h, Y.gpos[l]);
             v.cp_ptr[l] = at<int>(h, Y.cp_ptr[l]);
         }
         if (l >= 1) v.y[l] = at<double>(h, Y.y[l]);
@@ -288,8 +289,8 @@ int upload_plan(mas_handle* h, hipStream_t s) {
         HIP_TRY(put(Y.dom_blk[l], l == 0 ? h->translated[1] : P.dom_blk[l]));
         HIP_TRY(put(Y.dom_ab[l], P.dom_ab[l]));
         if (l >= 2) {
-            HIP_TRY(put(Y.anc1[l], P.anc1[l]));
-            HIP_TRY(put(Y.lead_pos[l], P.lead_pos[l]));
+            HIP_TRY(put(Y.ganc[l], P.ganc[l]));
+            HIP_TRY(put(Y.gpos[l], P.gpos[l]));
             HIP_TRY(put(Y.cp_ptr[l], P.cp_ptr[l]));
         }
     }
@@ -363,8 +364,11 @@ int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, con
     int k = 0;
     int rc = MAS_OK;
     DevState& st = *h->st_host;
-    for (;;) {
-        const int nb = std::min(opt.check_every, opt.max_iter - k);
+    // Iterations run in batches of check_every.  After each batch the device
+    // state is copied into a pinned slot; the host looks at a batch's copy
+    // only once the next batch is queued, so the device never waits for the
+    // host.  Kernels queued after a stop return at once.
+    auto batch = [&](int nb) -> int {
         for (int i = 0; i < nb; ++i) {
             ++k;
             HIP_TRY(timed(h, kKSpmv, s, [&] { return launch_spmv_pq(v, mixed, k, s); }));
@@ -376,22 +380,39 @@ int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, con
             }
             HIP_TRY(apply_iter(h, v, mixed, k, replaced, s));
         }
-        if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
-        if (st.status < 0) break;
-        if (st.done) {
-            if (st.status != kStatusConvergedRecurrence) break;
-            // stopped on the recurrence: confirm on the FP64 residual b - H x,
-            // which also replaces r; if it is not small enough, finish
-            // iteration st.iter with it and go on
-            k = st.iter;
-            HIP_TRY(launch_clear_stop(v, s));
-            HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidConfirm, v.r, s); }));
-            HIP_TRY(apply_iter(h, v, mixed, k, true, s));
-            if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
-            if (st.done || st.status < 0) break;
+        return MAS_OK;
+    };
+    int inflight = 0, head = 0, next = 0;  // batch copies not yet looked at; ring slots 1 + (0|1)
+    for (;;) {
+        while (inflight < 2 && k < opt.max_iter) {
+            if ((rc = batch(std::min(opt.check_every, opt.max_iter - k))) != MAS_OK) return rc;
+            HIP_TRY(hipMemcpyAsync(h->st_host + 1 + next, v.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipEventRecord(h->ev[kEvPoll0 + next], s));
+            next ^= 1;
+            ++inflight;
         }
-        if (k >= opt.max_iter) break;
+        if (inflight == 0) break;  // max_iter reached, every batch looked at
+        HIP_TRY(hipEventSynchronize(h->ev[kEvPoll0 + head]));
+        const DevState seen = h->st_host[1 + head];
+        head ^= 1;
+        --inflight;
+        if (seen.status >= 0 && !seen.done) continue;
+        // stopped: let the batch still queued run out (no-ops) and read the state
+        if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
+        inflight = 0;
+        head = next;
+        if (st.status != kStatusConvergedRecurrence) break;
+        // stopped on the recurrence: confirm on the FP64 residual b - H x,
+        // which also replaces r; if it is not small enough, finish iteration
+        // st.iter with it and go on
+        k = st.iter;
+        HIP_TRY(launch_clear_stop(v, s));
+        HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidConfirm, v.r, s); }));
+        HIP_TRY(apply_iter(h, v, mixed, k, true, s));
+        if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
+        if (st.done || st.status < 0) break;
     }
+    if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
     if (st.bb == 0.0)  // b = 0: the solution is x = b = 0 (also when an x0 was given)
         HIP_TRY(hipMemcpyAsync(v.x, v.b, sizeof(double) * 3 * v.NS, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_residual(v, kResidFinal, v.q, s));
@@ -478,11 +499,12 @@ int mas_build(mas_handle* h, const mas_bcsr* H, void* workspace, size_t ws_bytes
     if (ws_bytes < h->lay.total) return MAS_WORKSPACE_TOO_SMALL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!h->st_host) {
-        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->st_host), sizeof(DevState), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->st_host), 3 * sizeof(DevState), hipHostMallocDefault));
         HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->flag_host), sizeof(int), hipHostMallocDefault));
     }
     if (!h->events) {
-        for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
+        for (int i = 0; i < kEvCount; ++i)
+            HIP_TRY(hipEventCreateWithFlags(&h->ev[i], i >= kEvPoll0 ? hipEventDisableTiming : hipEventDefault));
         h->events = true;
     }
     h->ws = static_cast<char*>(workspace);

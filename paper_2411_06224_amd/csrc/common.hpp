@@ -91,6 +91,54 @@ __device__ inline double sum_partials(const double* __restrict__ p, int n, doubl
 
 __device__ inline bool finite(double x) { return x - x == 0.0; }
 
+// sum_partials split in two, so that the loads can be issued early and their
+// latency overlap other loads: partials_load() fetches thread t's bucket
+// entries p[t], p[t + 256], ... into registers (n <= 1024), partials_sum()
+// adds them in sum_partials' order (same bits) and folds the buckets.  For
+// n > 1024 partials_sum() falls back to sum_partials.
+struct PartialLoads {
+    double v[4];
+};
+
+__device__ inline PartialLoads partials_load(const double* __restrict__ p, int n) {
+    PartialLoads L;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = t + 256 * j;
+        L.v[j] = (t < 256 && i < n && n <= 1024) ? p[i] : 0.0;
+    }
+    return L;
+}
+
+__device__ inline double partials_sum(const PartialLoads& L, const double* __restrict__ p, int n, double* buf) {
+    if (n > 1024) return sum_partials(p, n, buf);
+    const int t = threadIdx.x;
+    if (t < 256) {
+        double s = 0.0;
+        if (t + 768 < n) {
+            s += (L.v[0] + L.v[1]) + (L.v[2] + L.v[3]);
+        } else {
+            if (t < n) s += L.v[0];
+            if (t + 256 < n) s += L.v[1];
+            if (t + 512 < n) s += L.v[2];
+        }
+        buf[t] = s;
+    }
+    __syncthreads();
+    if (t < 64) {
+        double s = (buf[t] + buf[t + 64]) + (buf[t + 128] + buf[t + 192]);
+        s = wave_sum(s);
+        if (t == 0) buf[0] = s;
+    }
+    __syncthreads();
+    const double r = buf[0];
+    __syncthreads();
+    return r;
+}
+
+
+
 inline int ceil_div(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
 inline int round_waves(int threads) { return (threads + 63) / 64 * 64; }
 

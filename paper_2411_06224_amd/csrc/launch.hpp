@@ -45,8 +45,9 @@ struct SolverView {
     const int* lead1;     // [NS]
     const int* anc;       // [(L-1)*NS]
     const int* g_u1;      // [G+1]
-    const int* anc1[kMaxLv];      // l >= 2: [S_1]
-    const int* lead_pos[kMaxLv];  // l >= 2: [S_1]
+    int W1;                       // restriction: most level-1 units in a group
+    const int* ganc[kMaxLv];      // l >= 2: [G * W1] level-l unit of each level-1 unit of each group (-1 pad)
+    const int* gpos[kMaxLv];      // l >= 2: [G * W1] its partial position, -1 if it writes none
     const int* cp_ptr[kMaxLv];    // l >= 2: [S_l + 1]
     // slot-ordered matrix (9 planes of nnzb values)
     double* H64;

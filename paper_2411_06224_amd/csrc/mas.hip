@@ -283,7 +283,8 @@ __device__ void convergence_decision(const SolverView& v, int mode, int k, doubl
 // Coarse levels l >= 1 (workgroups 1.. of the launch, one per domain, all
 // levels at once): r_l for the domain's N units -- level 1 straight from
 // r_1, higher levels as sums of the per-group partials the restriction left
-// for each unit (a contiguous range per unit, one wave per unit) -- then
+// for each unit (a contiguous range per unit; for N = 16 sixteen lanes per
+// unit, all units at once, else one wave per unit) -- then
 // y_l = Inv_{l,d} r_l.
 template <typename TI, int kN>
 __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab, int mode, int k, double tol,
@@ -303,8 +304,54 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
     const int u0 = d * N;
     const int nu = min(N, v.units[l] - u0);
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const TI* inv;
+    if constexpr (sizeof(TI) == 8)
+        inv = v.inv64[l];
+    else
+        inv = v.inv32[l];
+    inv += static_cast<long long>(d) * n * n;
+    // N = 16: four threads per row, each holding a quarter of the row's
+    // inverse entries, loaded before the gather so that both are in flight
+    constexpr int kParts = 4;
+    constexpr int kCols = kN > 0 ? (3 * kN + kParts - 1) / kParts : 1;
+    double pre[kCols];
+    const int prow = t % n, ppart = t / n;
+    if constexpr (kN > 0) {
+        if (t < kParts * n) {
+#pragma unroll
+            for (int j = 0; j < kCols; ++j) {
+                const int kk = ppart * kCols + j;
+                pre[j] = kk < n ? inv_load(inv + static_cast<long long>(kk) * n + prow) : 0.0;
+            }
+        }
+    }
     if (l == 1) {
         if (t < n) rl[t] = t < 3 * nu ? v.r1[3 * u0 + t] : 0.0;
+    } else if constexpr (kN == 16) {
+        // all 16 units at once: 16 lanes per unit stride over its partials,
+        // then fold within the 16-lane segment
+        const int* cp = v.cp_ptr[l];
+        const int a = t >> 4, sub = t & 15;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        if (a < nu) {
+            const int m0 = cp[u0 + a], m1 = cp[u0 + a + 1];
+            for (int m = m0 + sub; m < m1; m += 16) {
+                s0 += v.cpart[3 * m];
+                s1 += v.cpart[3 * m + 1];
+                s2 += v.cpart[3 * m + 2];
+            }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o, 16);
+            s1 += __shfl_xor(s1, o, 16);
+            s2 += __shfl_xor(s2, o, 16);
+        }
+        if (sub == 0) {
+            rl[3 * a] = s0;
+            rl[3 * a + 1] = s1;
+            rl[3 * a + 2] = s2;
+        }
     } else {
         const int* cp = v.cp_ptr[l];
         for (int a = w; a < N; a += 4) {
@@ -334,24 +381,28 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
         }
     }
     __syncthreads();
-    if (t < n) {
-        const TI* inv;
-        if constexpr (sizeof(TI) == 8)
-            inv = v.inv64[l];
-        else
-            inv = v.inv32[l];
-        inv += (long long)d * n * n + t;
-        double acc = 0.0;
-        if constexpr (kN > 0) {
+    if constexpr (kN > 0) {
+        __shared__ double quarter[kParts][3 * kN];
+        if (t < kParts * n) {
+            double a = 0.0;
 #pragma unroll
-            for (int kk = 0; kk < 3 * kN; ++kk) acc += inv_load(inv + kk * 3 * kN) * rl[kk];
-        } else {
-#pragma unroll 8
-            for (int kk = 0; kk < n; ++kk) acc += inv_load(inv + kk * n) * rl[kk];
+            for (int j = 0; j < kCols; ++j) {
+                const int kk = ppart * kCols + j;
+                if (kk < n) a += pre[j] * rl[kk];
+            }
+            quarter[ppart][prow] = a;
         }
+        __syncthreads();
+        if (t < n) v.y[l][3 * u0 + t] = ((quarter[0][t] + quarter[1][t]) + quarter[2][t]) + quarter[3][t];
+    } else if (t < n) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int kk = 0; kk < n; ++kk) acc += inv_load(inv + static_cast<long long>(kk) * n + t) * rl[kk];
         v.y[l][3 * u0 + t] = acc;
     }
 }
+
+constexpr int kPreLevels = 8;  // coarse levels whose corrections are prefetched
 
 // Level 0 over a group of D0 domains, one thread per DOF:
 //   z = Inv_{0,d} r_d + sum_{l >= 1} y_l[unit of the slot at level l]
@@ -368,7 +419,17 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
     const int nd = min(v.D0, v.M - g * v.D0);  // domains of this group
     const bool live = t < nd * n;
     const long long base = 3LL * g * v.RG;
+    const int slot = g * v.RG + t / 3, c = t % 3;
+    // coarse corrections of the slot (prolongation), loaded with r so that
+    // their latency ends before the inverse stream starts
+    int u[kPreLevels];
+#pragma unroll
+    for (int j = 0; j < kPreLevels; ++j)
+        u[j] = (live && j + 1 < v.L) ? v.anc[static_cast<long long>(j) * v.NS + slot] : -1;
     const double rv = live ? v.r[base + t] : 0.0;
+    double ycor[kPreLevels];
+#pragma unroll
+    for (int j = 0; j < kPreLevels; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
     if (t < 384) rs[t] = rv;
     __syncthreads();
     double zv = 0.0;
@@ -390,10 +451,12 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
 #pragma unroll 8
             for (int kk = 0; kk < n; ++kk) acc += inv_load(inv + kk * n) * rd[kk];
         }
-        const int slot = g * v.RG + t / 3, c = t % 3;
-        for (int l = 1; l < v.L; ++l) {
-            const int u = v.anc[(long long)(l - 1) * v.NS + slot];
-            if (u >= 0) acc += v.y[l][3 * u + c];
+#pragma unroll
+        for (int j = 0; j < kPreLevels; ++j)
+            if (u[j] >= 0) acc += ycor[j];
+        for (int l = kPreLevels + 1; l < v.L; ++l) {
+            const int uu = v.anc[static_cast<long long>(l - 1) * v.NS + slot];
+            if (uu >= 0) acc += v.y[l][3 * uu + c];
         }
         zv = acc;
         v.z[base + t] = zv;

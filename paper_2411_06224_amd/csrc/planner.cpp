@@ -414,6 +414,21 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
         }
     }
 
+    P.W1 = 1;
+    for (int g = 0; g < P.G; ++g) P.W1 = std::max(P.W1, P.g_u1[g + 1] - P.g_u1[g]);
+    P.ganc.assign(P.L, {});
+    P.gpos.assign(P.L, {});
+    for (int l = 2; l < P.L; ++l) {
+        P.ganc[l].assign(static_cast<size_t>(P.G) * P.W1, -1);
+        P.gpos[l].assign(static_cast<size_t>(P.G) * P.W1, -1);
+        for (int g = 0; g < P.G; ++g)
+            for (int t = P.g_u1[g]; t < P.g_u1[g + 1]; ++t) {
+                const size_t o = static_cast<size_t>(g) * P.W1 + (t - P.g_u1[g]);
+                P.ganc[l][o] = P.anc1[l][t];
+                P.gpos[l][o] = P.lead_pos[l][t];
+            }
+    }
+
     // ---- per-node units for reports
     P.sn.assign(static_cast<size_t>(P.L) * V, -1);
     for (int i = 0; i < V; ++i) {

@@ -58,6 +58,12 @@ struct Plan {
     std::vector<std::vector<int>> lead_pos;  // [l][S_1]
     std::vector<std::vector<int>> cp_ptr;    // [l][S_l + 1]
     int n_cpart = 0;                         // partial positions over all levels
+    // The same per group, padded so that a group's entries sit at a fixed
+    // place: ganc[l] / gpos[l] hold anc1[l] / lead_pos[l] of the group's
+    // level-1 units at [g * W1 + i] (i < W1 = the most level-1 units in a
+    // group; -1 past the group's own).
+    int W1 = 1;
+    std::vector<std::vector<int>> ganc, gpos;
     // Prolongation: unit of every slot at levels 1..L-1, [(l-1) * NS + slot], -1 = empty.
     std::vector<int> anc;
 

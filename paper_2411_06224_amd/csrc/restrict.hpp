@@ -10,11 +10,12 @@
 
 namespace maspcg {
 
-// Shared memory of the restriction, in doubles, for a group of RG slots and
-// L levels: r1s[3 RG] doubles + up0[RG], lead[RG], anc[(L-2) RG], pos[(L-2) RG] ints.
-__host__ __device__ inline int restrict_smem_doubles(int RG, int L) {
-    const int ints = 2 * RG + 2 * (L > 2 ? L - 2 : 0) * RG;
-    return 3 * RG + (ints + 1) / 2;
+// Shared memory of the restriction, in doubles, for a group of RG slots with
+// at most W1 level-1 units and L levels: r1s[3 W1] doubles + up0[RG],
+// lead[RG], anc[(L-2) W1], pos[(L-2) W1] ints.
+__host__ __device__ inline int restrict_smem_doubles(int RG, int W1, int L) {
+    const int ints = 2 * RG + 2 * (L > 2 ? L - 2 : 0) * W1;
+    return 3 * W1 + (ints + 1) / 2;
 }
 
 struct RestrictSmem {
@@ -25,20 +26,28 @@ struct RestrictSmem {
 __device__ inline RestrictSmem restrict_layout(const SolverView& v, double* sm) {
     RestrictSmem r;
     r.r1s = sm;
-    r.up0 = reinterpret_cast<int*>(sm + 3 * v.RG);
+    r.up0 = reinterpret_cast<int*>(sm + 3 * v.W1);
     r.lead = r.up0 + v.RG;
     r.anc = r.lead + v.RG;
-    r.pos = r.anc + (v.L > 2 ? v.L - 2 : 0) * v.RG;
+    r.pos = r.anc + (v.L > 2 ? v.L - 2 : 0) * v.W1;
     return r;
 }
 
+// The group's range of level-1 units: first unit and count.
+struct GroupUnits {
+    int lo, n;
+};
+
 // Loads the group's plan (level-1 unit and writer flag of every slot, and
 // for every level l >= 2 the ancestor and writer position of every level-1
-// unit of the group) into shared memory.  Needs a barrier before use.
-__device__ inline void restrict_prefetch(const SolverView& v, int g, double* sm) {
-    if (v.L < 2) return;
+// unit of the group, from the per-group padded tables, so that no load
+// waits for another) into shared memory.  Needs a barrier before use.
+// Returns the group's level-1 unit range for restrict_group.
+__device__ inline GroupUnits restrict_prefetch(const SolverView& v, int g, double* sm) {
+    if (v.L < 2) return GroupUnits{0, 0};
     const RestrictSmem S = restrict_layout(v, sm);
-    const int RG = v.RG, slot0 = g * RG;
+    const int RG = v.RG, W = v.W1, slot0 = g * RG;
+    const int u1_lo = v.g_u1[g], n1 = v.g_u1[g + 1] - u1_lo;
     for (int i = threadIdx.x; i < RG; i += blockDim.x) {
         const int slot = slot0 + i;
         const bool in = slot < v.NS;
@@ -46,14 +55,14 @@ __device__ inline void restrict_prefetch(const SolverView& v, int g, double* sm)
         S.lead[i] = in ? v.lead1[slot] : -1;
     }
     if (v.L > 2) {
-        const int u1_lo = v.g_u1[g], n1 = v.g_u1[g + 1] - u1_lo;
-        const int tot = (v.L - 2) * n1;
+        const int tot = (v.L - 2) * W;
         for (int o = threadIdx.x; o < tot; o += blockDim.x) {
-            const int l = 2 + o / n1, i = o - (l - 2) * n1;
-            S.anc[(l - 2) * RG + i] = v.anc1[l][u1_lo + i];
-            S.pos[(l - 2) * RG + i] = v.lead_pos[l][u1_lo + i];
+            const int l = 2 + o / W, i = o - (l - 2) * W;
+            S.anc[o] = v.ganc[l][static_cast<long long>(g) * W + i];
+            S.pos[o] = v.gpos[l][static_cast<long long>(g) * W + i];
         }
     }
+    return GroupUnits{u1_lo, n1};
 }
 
 // rs[3*RG]: the group's residual in slot order (zero on slots >= NS), and
@@ -63,11 +72,11 @@ __device__ inline void restrict_prefetch(const SolverView& v, int g, double* sm)
 // one partial sum per (group, level-l supernode) at the position the plan
 // assigns (summed over the group's level-1 supernodes below it, ascending).
 // No atomics: every output has exactly one writer.
-__device__ inline void restrict_group(const SolverView& v, int g, const double* rs, double* sm) {
+__device__ inline void restrict_group(const SolverView& v, GroupUnits gu, const double* rs, double* sm) {
     if (v.L < 2) return;
     const RestrictSmem S = restrict_layout(v, sm);
     const int RG = v.RG, N = v.N;
-    const int u1_lo = v.g_u1[g], n1 = v.g_u1[g + 1] - u1_lo;
+    const int u1_lo = gu.lo, n1 = gu.n;
     for (int o = threadIdx.x; o < 3 * RG; o += blockDim.x) {
         const int ls = o / 3, c = o - 3 * ls;
         const int u = S.lead[ls];
@@ -85,9 +94,9 @@ __device__ inline void restrict_group(const SolverView& v, int g, const double* 
         for (int o = threadIdx.x; o < tot; o += blockDim.x) {
             const int li = o / 3, c = o - 3 * li;
             const int l = li / n1, i = li - l * n1;
-            const int pos = S.pos[l * RG + i];
+            const int pos = S.pos[l * v.W1 + i];
             if (pos < 0) continue;
-            const int* anc = S.anc + l * RG;
+            const int* anc = S.anc + l * v.W1;
             const int a = anc[i];
             double s = 0.0;
             for (int j = 0; j < n1; ++j)

@@ -68,7 +68,7 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
     const int kb = rp[r0], ke = rp[r1];
     for (int cs = kb; cs < ke; cs += kChunk) {
         const int ce = min(cs + kChunk, ke);
-#pragma unroll 4
+#pragma unroll 8
         for (int k = cs + t; k < ce; k += kThreads) {
             const int j = ci[k];
             const double x0 = x.at(3 * j), x1 = x.at(3 * j + 1), x2 = x.at(3 * j + 2);
@@ -120,13 +120,15 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     if (v.st->done) return;
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
-    // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
+    // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded
+    // it (loaded before the partial sum's barriers)
+    const double rk2 = v.st->rho[k & 1];
     const double rk1 = sum_partials(v.P_rho[(k - 1) & 1], v.G, buf);
     if (g == 0 && threadIdx.x == 0) v.st->rho[(k - 1) & 1] = rk1;
     double beta = 0.0;
     const double* pold = v.z;  // k = 1: p_1 = z_0 (+ 0 * z_0)
     if (k > 1) {
-        beta = rk1 / v.st->rho[k & 1];
+        beta = rk1 / rk2;
         pold = v.p[(k - 1) & 1];
     }
     const XDir dir{v.z, pold, beta};
@@ -161,7 +163,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     double acc[2];
-    restrict_prefetch(v, g, dyn + 3 * v.RG);
+    const GroupUnits gu = restrict_prefetch(v, g, dyn + 3 * v.RG);
     stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, XVec{v.x}, r0, r1, prod, acc);
     double rr = 0.0, bb = 0.0;
     double* rs = dyn;
@@ -187,7 +189,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
         v.P_rr[g] = rr;
         if (kMode == kResidInit) v.P_bb[g] = bb;
     }
-    if (kMode != kResidFinal) restrict_group(v, g, rs, dyn + 3 * v.RG);
+    if (kMode != kResidFinal) restrict_group(v, gu, rs, dyn + 3 * v.RG);
 }
 
 }  // namespace
@@ -214,7 +216,7 @@ hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s) {
 
 hipError_t launch_residual(const SolverView& v, int mode, double* out, hipStream_t s) {
     dim3 g(v.G), b(kThreads);
-    const size_t shmem = sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.L));
+    const size_t shmem = sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L));
     switch (mode) {
         case kResidInit: launch_kernel(k_residual<kResidInit>, g, b, shmem, s, v, out); break;
         case kResidReplace: launch_kernel(k_residual<kResidReplace>, g, b, shmem, s, v, out); break;

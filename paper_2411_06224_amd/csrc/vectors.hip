@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(kVecThreads) k_perm_out(int V, const int* __re
 
 // Shared memory of the group kernels: rs[3*RG] + restriction scratch + 256.
 inline size_t group_smem(const SolverView& v) {
-    return sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.L) + 256);
+    return sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L) + 256);
 }
 
 // r = b, x = 0, partials of ||b||^2 (as both ||r||^2 and ||b||^2), and the
@@ -82,9 +82,9 @@ inline size_t group_smem(const SolverView& v) {
 __global__ void k_init_rhs(SolverView v) {
     extern __shared__ double sm[];
     double* rs = sm;
-    double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.L);
+    double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L);
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
-    restrict_prefetch(v, g, sm + 3 * v.RG);
+    const GroupUnits gu = restrict_prefetch(v, g, sm + 3 * v.RG);
     const long long i = 3LL * g * v.RG + t;
     double bv = 0.0;
     if (t < 3 * v.RG) {
@@ -100,7 +100,7 @@ __global__ void k_init_rhs(SolverView v) {
         v.P_rr[g] = bb;
         v.P_bb[g] = bb;
     }
-    restrict_group(v, g, rs, sm + 3 * v.RG);
+    restrict_group(v, gu, rs, sm + 3 * v.RG);
 }
 
 // Iteration k: alpha = rho_{k-1} / sigma_k (sigma summed here from the group
@@ -110,11 +110,10 @@ __global__ void k_init_rhs(SolverView v) {
 __global__ void k_update(SolverView v, int k) {
     extern __shared__ double sm[];
     double* rs = sm;
-    double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.L);
-    if (v.st->done) return;
+    double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L);
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
-    // issue every independent load before the first barrier
-    restrict_prefetch(v, g, sm + 3 * v.RG);
+    // issue every independent load (the stop flag's included) before the
+    // first wait; after a stop nothing is written
     const long long i = 3LL * g * v.RG + t;
     const bool own = t < 3 * v.RG && i < 3LL * v.NS;
     const double* pk = v.p[k & 1];
@@ -125,8 +124,11 @@ __global__ void k_update(SolverView v, int k) {
         rv0 = v.r[i];
         qv = v.q[i];
     }
-    const double sigma = sum_partials(v.P_sigma, v.G, scratch);
+    const PartialLoads sig = partials_load(v.P_sigma, v.G);
     const double rho = v.st->rho[(k - 1) & 1];
+    const GroupUnits gu = restrict_prefetch(v, g, sm + 3 * v.RG);
+    if (v.st->done) return;
+    const double sigma = partials_sum(sig, v.P_sigma, v.G, scratch);
     if (!(sigma > 0.0) || !finite(sigma) || !finite(rho)) {
         if (g == 0 && t == 0) {
             v.st->status = (finite(sigma) && finite(rho)) ? -2 : -6;
@@ -145,7 +147,7 @@ __global__ void k_update(SolverView v, int k) {
     if (t < 3 * v.RG) rs[t] = rv;
     const double rr = block_sum(rv * rv, scratch);  // its barriers also publish rs and the plan
     if (t == 0) v.P_rr[g] = rr;
-    restrict_group(v, g, rs, sm + 3 * v.RG);
+    restrict_group(v, gu, rs, sm + 3 * v.RG);
 }
 
 // Restriction of the current r only (preconditioner apply outside PCG).
@@ -153,11 +155,11 @@ __global__ void k_restrict(SolverView v) {
     extern __shared__ double sm[];
     double* rs = sm;
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
-    restrict_prefetch(v, g, sm + 3 * v.RG);
+    const GroupUnits gu = restrict_prefetch(v, g, sm + 3 * v.RG);
     const long long i = 3LL * g * v.RG + t;
     if (t < 3 * v.RG) rs[t] = i < 3LL * v.NS ? v.r[i] : 0.0;
     __syncthreads();
-    restrict_group(v, g, rs, sm + 3 * v.RG);
+    restrict_group(v, gu, rs, sm + 3 * v.RG);
 }
 
 // dL/dH_ij = -lambda_i x_j^T on every stored block, caller order and layout.

@@ -1,0 +1,158 @@
+"""GPU checks on the full-size 48^3 cube (117,649 nodes, 20,000 contact-like
+couplings) beyond the E = 1e6 case of test_gpu_parity.py, in the launch
+configuration the benchmark times:
+
+  E sweep (1e4, 1e8), FP64   SpMV rows (1e-14 |H||x|), MAS apply (1e-10), 10 fixed
+                             PCG iterations (1e-10) against the oracle; the converged
+                             solve meets tol on the FP64 residual b - H x
+  mixed precision            E in {1e6, 1e8}, tol in {1e-4, 1e-6}: the FP64 residual
+                             meets tol (parity unpinned beyond that: the error against
+                             an FP64 solve is printed)
+  adjoint, E = 1e7           L = 1/2 ||x - x*||^2: dL/dH from the adjoint solve against
+                             central differences on 64 random symmetric block pairs,
+                             <= 1e-4 relative; the mixed path's gradient error printed
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import large_cube
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2411_06224_amd as mp
+
+    mp.load()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+
+
+def _setup(s, dev, precision="f64"):
+    from paper_2411_06224_amd import BlockMatrix, MasPcg
+
+    H = BlockMatrix.from_numpy(s.row_ptr, s.col_idx, s.val, device=dev)
+    S = MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16, precision=precision)
+    S.build(H)
+    return H, S
+
+
+def _true_rel(s, x):
+    return np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, x)) / np.linalg.norm(s.b)
+
+
+@pytest.mark.parametrize("E", [1e4, 1e8])
+def test_large_cube_E_sweep(dev, E):
+    from paper_2411_06224_amd import bcsr_spmv
+
+    _say("48^3 E sweep", E)
+    s = large_cube(E)
+    H, S = _setup(s, dev)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(3 * s.n)
+    y = bcsr_spmv(H, _t(x, dev)).cpu().numpy()
+    ref = oracle.spmv(s.row_ptr, s.col_idx, s.val, x)
+    bound = oracle.spmv(s.row_ptr, s.col_idx, np.abs(s.val), np.abs(x))
+    assert np.all(np.abs(y - ref) <= 1e-14 * bound + 1e-300)
+    P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=16, gptr=s.gptr, gadj=s.gadj)
+    r = rng.standard_normal(3 * s.n)
+    z = S.apply(_t(r, dev)).cpu().numpy()
+    zr = P.apply(r)
+    assert np.linalg.norm(z - zr) <= 1e-10 * np.linalg.norm(zr)
+    xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+    xg, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10)
+    assert res["iterations"] == it == 10
+    assert np.linalg.norm(xg.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+    for tol in (1e-4, 1e-8):
+        xg, res = S.solve(H, _t(s.b, dev), tol=tol)
+        true = _true_rel(s, xg.cpu().numpy())
+        print(f"E={E:g} tol={tol:g}: {res['iterations']} iterations, true residual {true:.3e}")
+        assert res["status"] == 0 and true <= tol * 1.01
+
+
+@pytest.mark.parametrize("E", [1e6, 1e8])
+def test_large_cube_mixed(dev, E):
+    _say("48^3 mixed", E)
+    s = large_cube(E)
+    H, S64 = _setup(s, dev)
+    xref, _ = S64.solve(H, _t(s.b, dev), tol=1e-10)
+    xref = xref.cpu().numpy()
+    _, S = _setup(s, dev, precision="mixed")
+    for tol in (1e-4, 1e-6):
+        x, res = S.solve(H, _t(s.b, dev), tol=tol)
+        xv = x.cpu().numpy()
+        true = _true_rel(s, xv)
+        err = np.linalg.norm(xv - xref) / np.linalg.norm(xref)
+        print(f"mixed E={E:g} tol={tol:g}: {res['iterations']} iterations, true residual {true:.3e}, "
+              f"error vs FP64 solve {err:.3e}")
+        assert res["status"] == 0 and true <= tol
+
+
+def test_large_cube_adjoint_fd(dev):
+    _say("48^3 adjoint vs central differences, E = 1e7")
+    s = large_cube(1e7)
+    H, S = _setup(s, dev)
+    b = _t(s.b, dev)
+    xstar = np.random.default_rng(2024).standard_normal(3 * s.n)
+    tol = 1e-12
+
+    def loss(Hm):
+        x, res = S.solve(Hm, b, tol=tol, allow_not_converged=False)
+        return 0.5 * float(np.sum((x.cpu().numpy() - xstar) ** 2)), x
+
+    L0, x = loss(H)
+    lam, G, res = S.adjoint(H, x, x - _t(xstar, dev), tol=tol)
+    G = G.cpu().numpy()
+
+    # 64 random stored blocks (i, j) and their mirrors (j, i): H stays symmetric
+    rows = np.repeat(np.arange(s.n), np.diff(s.row_ptr))
+    rng = np.random.default_rng(7)
+    picks = rng.choice(len(s.col_idx), size=64, replace=False)
+    fd, ad = [], []
+    for k in picks:
+        i, j = int(rows[k]), int(s.col_idx[k])
+        lo, hi = s.row_ptr[j], s.row_ptr[j + 1]
+        m = lo + int(np.searchsorted(s.col_idx[lo:hi], i))
+        assert s.col_idx[m] == i
+        D = rng.standard_normal((3, 3))
+        if i == j:
+            D = 0.5 * (D + D.T)
+        eps = 1e-5 * np.abs(s.val.reshape(-1, 3, 3)[k]).max()
+        vals = []
+        for sgn in (1.0, -1.0):
+            val = H.val.clone()
+            val[k] += torch.as_tensor(sgn * eps * D, device=dev)
+            if m != k:
+                val[m] += torch.as_tensor(sgn * eps * D.T, device=dev)
+            from paper_2411_06224_amd import BlockMatrix
+
+            vals.append(loss(BlockMatrix(H.row_ptr, H.col_idx, val))[0])
+        fd.append((vals[0] - vals[1]) / (2 * eps))
+        ad.append(np.sum(G[k] * D) + (np.sum(G[m] * D.T) if m != k else 0.0))
+    fd, ad = np.array(fd), np.array(ad)
+    rel = np.linalg.norm(fd - ad) / np.linalg.norm(ad)
+    print(f"adjoint vs central differences on 64 block pairs: relative error {rel:.3e}")
+    assert rel <= 1e-4
+
+    # mixed-precision forward (tol 1e-6) and adjoint: gradient error stated
+    _, Sm = _setup(s, dev, precision="mixed")
+    xm, _ = Sm.solve(H, b, tol=1e-6)
+    lam_m, G_m, _ = Sm.adjoint(H, xm, xm - _t(xstar, dev), tol=1e-6)
+    gerr = np.linalg.norm(G_m.cpu().numpy() - G) / np.linalg.norm(G)
+    print(f"mixed forward + adjoint at 1e-6: dL/dH relative error {gerr:.3e}")

@@ -4,7 +4,8 @@ Tolerances:
   SpMV (FP64)             |y - y_ref|_i <= 1e-14 (|H||x|)_i + tiny
   MAS apply (FP64)        ||z - z_ref|| <= 1e-10 ||z_ref||
   PCG, fixed iterations   ||x_k - x_k,ref|| <= 1e-10 ||x_k,ref||
-  PCG, converged          both meet tol on the true residual; iteration counts within +-2
+  PCG, converged          both meet tol on the true residual; the iteration count within
+                          +-2 of the oracle's counts for b perturbed at the rounding level
   tight solve             ||x - x_ref|| <= 1e-10 ||x_ref|| at tol 1e-13
   mixed precision         true FP64 residual <= tol; error vs the FP64 oracle printed
   gradients               vs dense FP64 gradient <= 1e-8 relative
@@ -61,6 +62,18 @@ def _oracle(s, N=16, max_levels=0, graph=True):
     if graph:
         return oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels, gptr=s.gptr, gadj=s.gadj)
     return oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels)
+
+
+def _oracle_count_range(P, b, tol, n=8):
+    """Oracle iteration counts for b and for b perturbed at the rounding level
+    (relative 1e-15).  On an ill-conditioned system the arithmetic fixes
+    PCG's iteration count only up to this spread (the contact cube at 1e-6
+    spans 226-230), so the GPU count is checked against it, +-2."""
+    rng = np.random.default_rng(123)
+    its = [P.pcg(b, tol=tol)[2]]
+    for _ in range(n - 1):
+        its.append(P.pcg(b * (1.0 + 1e-15 * rng.standard_normal(b.shape)), tol=tol)[2])
+    return min(its) - 2, max(its) + 2
 
 
 def _absH_absx(s, x):
@@ -186,7 +199,8 @@ def test_pcg_converged(dev, name, N, tol):
     S.build(H)
     x, res = S.solve(H, _t(s.b, dev), tol=tol)
     assert res["status"] == 0 and st == 0
-    assert abs(res["iterations"] - it) <= 2
+    lo, hi = _oracle_count_range(P, s.b, tol)
+    assert lo <= res["iterations"] <= hi, (res["iterations"], it, lo, hi)
     assert res["true_rel_residual"] <= tol * 1.01
     xv = x.cpu().numpy()
     true = np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) / np.linalg.norm(s.b)
@@ -294,7 +308,8 @@ def test_pcg_long_range_couplings(dev):
     assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
     xr, st, it, *_ = P.pcg(s.b, tol=1e-8)
     x, res = S.solve(H, _t(s.b, dev), tol=1e-8)
-    assert res["status"] == 0 and st == 0 and abs(res["iterations"] - it) <= 2
+    lo, hi = _oracle_count_range(P, s.b, 1e-8)
+    assert res["status"] == 0 and st == 0 and lo <= res["iterations"] <= hi
     xv = x.cpu().numpy()
     assert np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) <= 1.01e-8 * np.linalg.norm(s.b)
 
