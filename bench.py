@@ -65,6 +65,7 @@ def algorithmic_bytes(info, mixed):
     """Bytes each hot kernel must move once per launch (no re-reads)."""
     V, N, L = info["n_rows"], info["domain_size"], info["levels"]
     nnzb = info["nnzb"]
+    nsb = info["stored_blocks"]
     NS = info["parts"] * N
     n = 3 * N
     vb = 8 * 3 * NS  # one slot-ordered FP64 vector
@@ -72,9 +73,11 @@ def algorithmic_bytes(info, mixed):
     inv = 4 if mixed else 8
     coarse_y = sum(8 * 3 * info["domains"][l] * N for l in range(1, L))
     out = {
-        # values + column index + row pointer; z and the previous direction
-        # read once (the direction update is fused in), new direction and q written
-        "spmv": nnzb * (val + 4) + 4 * (NS + 1) + 4 * vb,
+        # stored blocks (each block pair inside a work group once): values,
+        # column index and local row; row pointers and transposed-entry lists;
+        # z and the previous direction read once (the direction update is
+        # fused in), new direction and q written
+        "spmv": nsb * (val + 4 + 1) + 8 * (NS + 1) + 4 * (nnzb - nsb) + 4 * vb,
         # level-0 inverses, r read, z written, per-slot coarse ids, coarse corrections
         "apply_level0": info["domains"][0] * n * n * inv + 2 * vb + 4 * (L - 1) * NS + coarse_y,
         # coarse inverses, restricted residual read, y written
@@ -252,6 +255,30 @@ def main():
         }
         log(f"mixed solve: {ms_mixed:.3f} ms, {mres['iterations']} its, true res {mres['true_rel_residual']:.3e}")
         msolver.close()
+
+        # ordering ablation (Sec. 3.1): level-0 domains of consecutive nodes in
+        # Morton order of the positions instead of the connectivity-aware
+        # partition; same hierarchy construction, same solver
+        t0 = time.perf_counter()
+        osolver = mp.MasPcg(s.row_ptr, s.col_idx, domain_size=args.domain_size,
+                            partition=mp.morton_partition(s.meta["positions"], args.domain_size))
+        t_sym_m = time.perf_counter() - t0
+        step(osolver, args.tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, ores = step(osolver, args.tol)
+        torch.cuda.synchronize()
+        ms_morton = 1e3 * (time.perf_counter() - t0) / args.steps
+        oinf = osolver.info()
+        out["ordering_ablation"] = {
+            "connectivity": {"iterations": res["iterations"], "ms_per_solve": round(ms_per_step, 4),
+                             "levels": info["levels"]},
+            "morton": {"iterations": ores["iterations"], "ms_per_solve": round(ms_morton, 4),
+                       "levels": oinf["levels"], "symbolic_ms": round(1e3 * t_sym_m, 1)},
+        }
+        log(f"Morton ordering: {ores['iterations']} its, {ms_morton:.3f} ms, {oinf['levels']} levels")
+        osolver.close()
 
         # forward + adjoint (loss 0.5 ||x - x*||^2, FP32 dL/dH) vs forward
         xt = torch.as_tensor(np.random.default_rng(4).standard_normal(3 * s.n), device=dev)

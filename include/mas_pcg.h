@@ -109,6 +109,10 @@ typedef struct {
     int32_t coarse_nnzb[MAS_MAX_LEVELS]; /* stored blocks of the level-l coarse matrix (l >= 1) */
     int64_t workspace_bytes;
     int64_t inverse_bytes;            /* bytes of domain inverses (all levels, as stored) */
+    int32_t stored_blocks;            /* blocks of H the solver keeps in domain order: fewer than
+                                         nnzb when each pair of blocks inside a work group of
+                                         domains is stored once (symmetric storage) */
+    int32_t reserved;
 } mas_info;
 
 typedef struct mas_handle mas_handle;
@@ -134,6 +138,18 @@ void mas_destroy(mas_handle* h);
  * diagonal block, asymmetric pattern). */
 int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
                 const int32_t* g_ptr, const int32_t* g_adj);
+
+/* mas_analyze with a caller-given level-0 partition instead of the
+ * connectivity-aware bisection, e.g. consecutive nodes in Morton (Z-order)
+ * of their positions, the domain ordering of the earlier MAS preconditioner
+ * that Sec. 3.1 compares against.  part[n_rows] (host) puts node i in
+ * level-0 domain part[i], 0 <= part[i] < n_parts; every domain must hold
+ * 1..domain_size nodes.  Slots, hierarchy and plans then follow as in
+ * mas_analyze (slack reported as 0).
+ * Errors: MAS_INVALID_ARG (as mas_analyze, plus a part id out of range, an
+ * empty part or one with more than domain_size nodes). */
+int mas_analyze_partition(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr,
+                          const int32_t* col_idx, const int32_t* part, int32_t n_parts);
 
 /* Device bytes the handle needs (valid after mas_analyze; 0 before). */
 size_t mas_workspace_size(const mas_handle* h);

@@ -9,6 +9,7 @@ fails loudly if the library has not been built.
 from ._lib import LibraryMissing, MasError, load
 from .solver import BlockMatrix, MasPcg, bcsr_spmv
 from .autograd import MasPcgSolve, mas_pcg_solve
+from .ordering import morton_codes, morton_partition
 
 __all__ = [
     "BlockMatrix",
@@ -16,6 +17,8 @@ __all__ = [
     "bcsr_spmv",
     "MasPcgSolve",
     "mas_pcg_solve",
+    "morton_codes",
+    "morton_partition",
     "LibraryMissing",
     "MasError",
     "load",

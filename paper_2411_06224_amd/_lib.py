@@ -27,6 +27,7 @@ SYMBOLS = (
     "mas_create",
     "mas_destroy",
     "mas_analyze",
+    "mas_analyze_partition",
     "mas_workspace_size",
     "mas_build",
     "mas_apply",
@@ -94,6 +95,8 @@ class MasInfo(ctypes.Structure):
         ("coarse_nnzb", ctypes.c_int32 * MAS_MAX_LEVELS),
         ("workspace_bytes", ctypes.c_int64),
         ("inverse_bytes", ctypes.c_int64),
+        ("stored_blocks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -122,6 +125,8 @@ def load():
     L.mas_destroy.restype = None
     L.mas_analyze.argtypes = [vp, i32, i32, vp, vp, vp, vp]
     L.mas_analyze.restype = ctypes.c_int
+    L.mas_analyze_partition.argtypes = [vp, i32, i32, vp, vp, vp, i32]
+    L.mas_analyze_partition.restype = ctypes.c_int
     L.mas_workspace_size.argtypes = [vp]
     L.mas_workspace_size.restype = sz
     L.mas_build.argtypes = [vp, P(MasBcsr), vp, sz, vp]

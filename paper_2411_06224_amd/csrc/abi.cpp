@@ -21,7 +21,7 @@ constexpr size_t kAlign = 256;
 
 struct Layout {
     size_t total = 0;
-    size_t remap, map, perm_src, rp0, ci0, lead1, anc, g_u1;
+    size_t remap, map, perm_src, rp0, ci0, lead1, anc, g_u1, srp, sci, srow, tptr, tidx;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
     size_t ganc[kMaxLv], gpos[kMaxLv], cp_ptr[kMaxLv];
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
@@ -133,12 +133,20 @@ void make_layout(mas_handle* h) {
     const int n = 3 * P.N;
     Y.remap = Y.take(I * P.NS);
     Y.map = Y.take(I * P.V);
-    Y.perm_src = Y.take(I * P.nnzb);
+    const size_t nsb = P.sym ? P.sci.size() : static_cast<size_t>(P.nnzb);
+    Y.perm_src = Y.take(I * nsb);
     Y.rp0 = Y.take(I * (P.NS + 1));
     Y.ci0 = Y.take(I * P.nnzb);
     Y.lead1 = Y.take(I * P.NS);
     Y.anc = Y.take(I * P.anc.size());
     Y.g_u1 = Y.take(I * P.g_u1.size());
+    if (P.sym) {
+        Y.srp = Y.take(I * P.srp.size());
+        Y.sci = Y.take(I * P.sci.size());
+        Y.srow = Y.take(P.srow.size());
+        Y.tptr = Y.take(I * P.tptr.size());
+        Y.tidx = Y.take(I * P.tidx.size());
+    }
     for (int l = 0; l < P.L; ++l) {
         if (l >= 1) {
             Y.red_ptr[l] = Y.take(I * P.red_ptr[l].size());
@@ -153,8 +161,8 @@ void make_layout(mas_handle* h) {
             Y.cp_ptr[l] = Y.take(I * P.cp_ptr[l].size());
         }
     }
-    Y.H64 = Y.take(Dd * 9 * P.nnzb);
-    Y.H32 = mixed ? Y.take(F * 9 * P.nnzb) : 0;
+    Y.H64 = Y.take(Dd * 9 * nsb);
+    Y.H32 = mixed ? Y.take(F * 9 * nsb) : 0;
     for (int l = 1; l < P.L; ++l) Y.A[l] = Y.take(Dd * 9 * P.ciA[l].size());
     for (int l = 0; l < P.L; ++l) {
         const size_t cnt = static_cast<size_t>(P.ndom[l]) * n * n;
@@ -196,6 +204,16 @@ SolverView view(const mas_handle* h) {
     v.D0 = P.D0;
     v.RG = P.RG;
     v.G = P.G;
+    v.sym = P.sym ? 1 : 0;
+    v.nsb = P.sym ? static_cast<int>(P.sci.size()) : P.nnzb;
+    v.maxT = P.maxT;
+    if (P.sym) {
+        v.srp = at<int>(h, Y.srp);
+        v.sci = at<int>(h, Y.sci);
+        v.srow = at<uint8_t>(h, Y.srow);
+        v.tptr = at<int>(h, Y.tptr);
+        v.tidx = at<int>(h, Y.tidx);
+    }
     v.W1 = P.W1;
     for (int l = 0; l < P.L; ++l) {
         v.units[l] = P.units[l];
@@ -274,7 +292,14 @@ int upload_plan(mas_handle* h, hipStream_t s) {
     };
     HIP_TRY(put(Y.remap, P.remap));
     HIP_TRY(put(Y.map, P.map));
-    HIP_TRY(put(Y.perm_src, P.perm_src));
+    HIP_TRY(put(Y.perm_src, P.sym ? P.sperm : P.perm_src));
+    if (P.sym) {
+        HIP_TRY(put(Y.srp, P.srp));
+        HIP_TRY(put(Y.sci, P.sci));
+        HIP_TRY(hipMemcpyAsync(h->ws + Y.srow, P.srow.data(), P.srow.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(put(Y.tptr, P.tptr));
+        HIP_TRY(put(Y.tidx, P.tidx));
+    }
     HIP_TRY(put(Y.rp0, P.rp0));
     HIP_TRY(put(Y.ci0, P.ci0));
     HIP_TRY(put(Y.lead1, P.lead1));
@@ -465,12 +490,14 @@ void mas_destroy(mas_handle* h) {
     delete h;
 }
 
-int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
-                const int32_t* g_ptr, const int32_t* g_adj) {
+namespace {
+
+int analyze_impl(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                 const int32_t* g_ptr, const int32_t* g_adj, const int32_t* part, int32_t n_parts) {
     if (!h) return MAS_INVALID_ARG;
     Plan P;
     const std::string err = analyze(n_rows, nnzb, row_ptr, col_idx, g_ptr, g_adj, h->opts.domain_size,
-                                    h->opts.max_levels, P);
+                                    h->opts.max_levels, P, part, n_parts);
     if (!err.empty()) return MAS_INVALID_ARG;
     h->plan = std::move(P);
     h->analyzed = true;
@@ -487,6 +514,19 @@ int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_
     for (size_t k = 0; k < Q.dom_blk[0].size(); ++k) h->translated[1][k] = Q.perm_src[Q.dom_blk[0][k]];
     make_layout(h);
     return MAS_OK;
+}
+
+}  // namespace
+
+int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                const int32_t* g_ptr, const int32_t* g_adj) {
+    return analyze_impl(h, n_rows, nnzb, row_ptr, col_idx, g_ptr, g_adj, nullptr, 0);
+}
+
+int mas_analyze_partition(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr,
+                          const int32_t* col_idx, const int32_t* part, int32_t n_parts) {
+    if (!part) return MAS_INVALID_ARG;
+    return analyze_impl(h, n_rows, nnzb, row_ptr, col_idx, nullptr, nullptr, part, n_parts);
 }
 
 size_t mas_workspace_size(const mas_handle* h) { return (h && h->analyzed) ? h->lay.total : 0; }
@@ -600,6 +640,7 @@ int mas_get_info(const mas_handle* h, mas_info* out) {
     }
     out->workspace_bytes = static_cast<int64_t>(h->lay.total);
     out->inverse_bytes = static_cast<int64_t>(h->lay.inverse_bytes);
+    out->stored_blocks = P.sym ? static_cast<int32_t>(P.sci.size()) : P.nnzb;
     return MAS_OK;
 }
 

@@ -34,12 +34,20 @@ void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t 
 struct SolverView {
     int V, N, M, NS, L, nnzb;
     int D0, RG, G;  // work groups: D0 level-0 domains = RG slots; G groups
+    int sym;        // 1: H64 / H32 hold the group-symmetric storage (nsb blocks), 0: full slot-ordered H
+    int nsb;        // blocks of the stored slot-ordered H (H64 / H32 planes)
+    int maxT;       // most transposed entries of one group (symmetric storage)
     int units[kMaxLv];
     int ndom[kMaxLv];
     // plans
     const int* remap;     // [NS]
     const int* map;       // [V]
-    const int* perm_src;  // [nnzb] caller block of each slot-ordered block
+    const int* perm_src;  // [nsb] caller block of each stored block
+    const int* srp;       // symmetric storage: [NS+1] stored rows
+    const int* sci;       // [nsb] column slot of each stored block
+    const uint8_t* srow;  // [nsb] local row (slot - group start) of each stored block
+    const int* tptr;      // [NS+1] transposed entries of each row
+    const int* tidx;      // stored block of each transposed entry
     const int* rp0;       // [NS+1]
     const int* ci0;       // [nnzb]
     const int* lead1;     // [NS]
@@ -49,7 +57,7 @@ struct SolverView {
     const int* ganc[kMaxLv];      // l >= 2: [G * W1] level-l unit of each level-1 unit of each group (-1 pad)
     const int* gpos[kMaxLv];      // l >= 2: [G * W1] its partial position, -1 if it writes none
     const int* cp_ptr[kMaxLv];    // l >= 2: [S_l + 1]
-    // slot-ordered matrix (9 planes of nnzb values)
+    // stored slot-ordered matrix (9 planes of nsb values)
     double* H64;
     float* H32;
     // inverses per level, column-major (3N)^2 per domain

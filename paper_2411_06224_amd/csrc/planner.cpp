@@ -221,10 +221,50 @@ void domain_plan(const std::vector<int>& rp, const std::vector<int>& ci, int uni
     }
 }
 
+// Group-symmetric storage (see Plan::srp).
+void symmetric_storage(Plan& P) {
+    const int NS = P.NS, RG = P.RG;
+    P.srp.assign(NS + 1, 0);
+    P.sci.clear();
+    P.sperm.clear();
+    P.srow.clear();
+    std::vector<int> cnt(NS + 1, 0);
+    for (int s = 0; s < NS; ++s) {
+        const int r0 = s / RG * RG, r1 = std::min(r0 + RG, NS);
+        for (int k = P.rp0[s]; k < P.rp0[s + 1]; ++k) {
+            const int j = P.ci0[k];
+            if (j < r0 || j >= r1 || j >= s) {
+                P.sci.push_back(j);
+                P.sperm.push_back(P.perm_src[k]);
+                P.srow.push_back(static_cast<uint8_t>(s - r0));
+                if (j >= r0 && j < r1 && j > s) cnt[j + 1]++;
+            }
+        }
+        P.srp[s + 1] = static_cast<int>(P.sci.size());
+    }
+    P.tptr.assign(NS + 1, 0);
+    for (int s = 0; s < NS; ++s) P.tptr[s + 1] = P.tptr[s] + cnt[s + 1];
+    P.tidx.assign(P.tptr[NS], 0);
+    std::vector<int> fill(P.tptr.begin(), P.tptr.end() - 1);
+    for (int s = 0; s < NS; ++s) {
+        const int r0 = s / RG * RG, r1 = std::min(r0 + RG, NS);
+        for (int k = P.srp[s]; k < P.srp[s + 1]; ++k) {
+            const int j = P.sci[k];
+            if (j >= r0 && j < r1 && j > s) P.tidx[fill[j]++] = k;  // ascending k within row j
+        }
+    }
+    P.maxT = 0;
+    for (int g = 0; g < P.G; ++g) {
+        const int r0 = g * RG, r1 = std::min(r0 + RG, NS);
+        P.maxT = std::max(P.maxT, P.tptr[r1] - P.tptr[r0]);
+    }
+    P.sym = P.RG <= 256 && P.maxT <= kMaxTransposed;
+}
+
 }  // namespace
 
 std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* g_ptr,
-                    const int32_t* g_adj, int N, int max_levels, Plan& P) {
+                    const int32_t* g_adj, int N, int max_levels, Plan& P, const int32_t* part, int n_parts) {
     if (V <= 0 || nnzb < V || !row_ptr || !col_idx) return "empty matrix or null pattern";
     if (N < 1 || N > 40) return "domain_size must be in [1, 40]";
     if ((g_ptr == nullptr) != (g_adj == nullptr)) return "graph needs both g_ptr and g_adj";
@@ -256,10 +296,27 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
     P.N = N;
     P.nnzb = nnzb;
 
-    // ---- partition with the slack search of Eq. num_subdomains
-    const Graph g = g_ptr ? symmetrize(V, g_ptr, g_adj) : symmetrize(V, row_ptr, col_idx);
+    // ---- partition with the slack search of Eq. num_subdomains, or the
+    // caller's (every part 1..N nodes)
+    if (part) {
+        if (n_parts < 1 || n_parts > V) return "n_parts must be in [1, n_rows]";
+        std::vector<int> size(n_parts, 0);
+        for (int i = 0; i < V; ++i) {
+            if (part[i] < 0 || part[i] >= n_parts) return "part id out of range";
+            if (++size[part[i]] > N) return "a part holds more than domain_size nodes";
+        }
+        for (int q = 0; q < n_parts; ++q)
+            if (size[q] == 0) return "empty part";
+    }
+    const Graph g = part ? Graph() : (g_ptr ? symmetrize(V, g_ptr, g_adj) : symmetrize(V, row_ptr, col_idx));
     P.part.assign(V, 0);
     bool found = false;
+    if (part) {
+        P.part.assign(part, part + V);
+        P.M = n_parts;
+        P.No = 0;
+        found = true;
+    }
     for (int No = 0; No < N && !found; ++No) {
         const int M = (V + (N - No) - 1) / (N - No);
         Bisection(g).run(M, P.part);
@@ -428,6 +485,8 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
                 P.gpos[l][o] = P.lead_pos[l][t];
             }
     }
+
+    symmetric_storage(P);
 
     // ---- per-node units for reports
     P.sn.assign(static_cast<size_t>(P.L) * V, -1);

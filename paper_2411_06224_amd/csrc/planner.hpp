@@ -10,6 +10,9 @@
 namespace maspcg {
 
 constexpr int kMaxLevels = 16;
+// The symmetric storage keeps a group's transposed-entry list in LDS; groups
+// with more entries than this use the full storage.
+constexpr int kMaxTransposed = 4096;
 
 struct Plan {
     int V = 0;      // nodes (block rows of H)
@@ -67,11 +70,29 @@ struct Plan {
     // Prolongation: unit of every slot at levels 1..L-1, [(l-1) * NS + slot], -1 = empty.
     std::vector<int> anc;
 
+    // Group-symmetric storage of the slot-ordered H used by the solver's SpMV
+    // kernels (sym = true).  Within a group of RG rows a row keeps its blocks
+    // whose column lies outside the group and, of the group's own columns,
+    // only those >= the row (diagonal and upper part): an internal
+    // off-diagonal block (i, j), j > i, also stands for H_ji = H_ij^T, so each
+    // group-internal block pair is stored once.  srp[NS + 1] / sci / sperm:
+    // stored rows, columns (slots) and source blocks (caller order); srow:
+    // local row of each stored block; tptr[NS + 1] / tidx: for every row j
+    // the stored blocks (i, j), i < j, of its group, ascending.  maxT: the
+    // most transposed entries of one group.
+    bool sym = false;
+    std::vector<int> srp, sci, sperm, tptr, tidx;
+    std::vector<uint8_t> srow;
+    int maxT = 0;
+
     std::vector<int> sn;  // [L * V] unit of each node per level (level 0 = slot), for reports
 };
 
 // Returns "" on success or a message describing the invalid input.
+// part / n_parts (optional): a caller-given level-0 partition, used instead
+// of the recursive bisection of the node graph.
 std::string analyze(int n_rows, int nnzb, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* g_ptr,
-                    const int32_t* g_adj, int N, int max_levels, Plan& out);
+                    const int32_t* g_adj, int N, int max_levels, Plan& out, const int32_t* part = nullptr,
+                    int n_parts = 0);
 
 }  // namespace maspcg

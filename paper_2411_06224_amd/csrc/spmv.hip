@@ -91,6 +91,93 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
     }
 }
 
+// ---------------------------------------------------- symmetric storage
+// Group-symmetric storage: a group keeps one copy of each internal block
+// pair (the block with column >= row), used for both H_ij and H_ji = H_ij^T,
+// and its blocks with a column outside the group.  Per chunk of stored blocks
+// thread t multiplies block t, t + 256, ... by x of its column (to its row,
+// prod planes 0..2) and, for an internal off-diagonal block, its transpose by
+// x of its row (to its column, planes 3..5).  Owner o = 3 (row - r0) + c then
+// adds its row's direct products in column order and its transposed entries
+// in stored order.  xs: x on the group's own slots (LDS); external columns
+// are gathered through X; tl: the group's transposed entries (LDS).
+constexpr int kSymChunk = 512;
+
+template <typename T, typename X>
+__device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restrict__ H, X xg, const double* xs,
+                                           const int* tl, int tb0, int r0, int r1, double* prod, double (&acc)[2]) {
+    const int t = threadIdx.x;
+    const int nown = 3 * (r1 - r0), rows = r1 - r0;
+    const long long st = v.nsb;
+    int rb[2], re[2], tp[2], te[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        acc[q] = 0.0;
+        rb[q] = re[q] = tp[q] = te[q] = 0;
+        if (o < nown) {
+            const int row = r0 + o / 3;
+            rb[q] = v.srp[row];
+            re[q] = v.srp[row + 1];
+            tp[q] = v.tptr[row] - tb0;
+            te[q] = v.tptr[row + 1] - tb0;
+        }
+    }
+    const int kb = v.srp[r0], ke = v.srp[r1];
+    for (int cs = kb; cs < ke; cs += kSymChunk) {
+        const int ce = min(cs + kSymChunk, ke);
+#pragma unroll 4
+        for (int k = cs + t; k < ce; k += kThreads) {
+            const int j = v.sci[k];
+            const int r = v.srow[k];
+            const int jl = j - r0;
+            const bool internal = jl >= 0 && jl < rows;
+            double x0, x1, x2;
+            if (internal) {
+                x0 = xs[3 * jl];
+                x1 = xs[3 * jl + 1];
+                x2 = xs[3 * jl + 2];
+            } else {
+                x0 = xg.at(3 * j);
+                x1 = xg.at(3 * j + 1);
+                x2 = xg.at(3 * j + 2);
+            }
+            const double h0 = static_cast<double>(H[k]), h1 = static_cast<double>(H[st + k]),
+                         h2 = static_cast<double>(H[2 * st + k]), h3 = static_cast<double>(H[3 * st + k]),
+                         h4 = static_cast<double>(H[4 * st + k]), h5 = static_cast<double>(H[5 * st + k]),
+                         h6 = static_cast<double>(H[6 * st + k]), h7 = static_cast<double>(H[7 * st + k]),
+                         h8 = static_cast<double>(H[8 * st + k]);
+            const int e = k - cs;
+            prod[e] = h0 * x0 + h1 * x1 + h2 * x2;
+            prod[kSymChunk + e] = h3 * x0 + h4 * x1 + h5 * x2;
+            prod[2 * kSymChunk + e] = h6 * x0 + h7 * x1 + h8 * x2;
+            if (internal && jl != r) {
+                const double y0 = xs[3 * r], y1 = xs[3 * r + 1], y2 = xs[3 * r + 2];
+                prod[3 * kSymChunk + e] = h0 * y0 + h3 * y1 + h6 * y2;
+                prod[4 * kSymChunk + e] = h1 * y0 + h4 * y1 + h7 * y2;
+                prod[5 * kSymChunk + e] = h2 * y0 + h5 * y1 + h8 * y2;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int o = t + q * kThreads;
+            if (o < nown) {
+                const int c = o % 3;
+                const int lo = max(rb[q], cs), hi = min(re[q], ce);
+                for (int k = lo; k < hi; ++k) acc[q] += prod[c * kSymChunk + (k - cs)];
+                while (tp[q] < te[q]) {
+                    const int kk = tl[tp[q]];
+                    if (kk >= ce) break;
+                    acc[q] += prod[(3 + c) * kSymChunk + (kk - cs)];
+                    ++tp[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* __restrict__ rp,
                                                          const int* __restrict__ ci, const T* __restrict__ val,
@@ -133,7 +220,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     }
     const XDir dir{v.z, pold, beta};
     double acc[2];
-    stream_rows<T, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, dir, r0, r1, prod, acc);
+    stream_rows<T, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nsb}, dir, r0, r1, prod, acc);
     double* pk = v.p[k & 1];
     double part = 0.0;
 #pragma unroll
@@ -151,20 +238,93 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     if (threadIdx.x == 0) v.P_sigma[g] = part;
 }
 
+// k_spmv_pq on the group-symmetric storage: the group forms the new
+// direction on its own slots first (into LDS and p_k) and gathers it only for
+// columns outside the group.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T* __restrict__ H, int k) {
+    __shared__ double prod[6 * kSymChunk];
+    __shared__ double buf[256];
+    extern __shared__ double dyn[];  // xs[3 RG] doubles + tl[maxT] ints
+    if (v.st->done) return;
+    const int t = threadIdx.x;
+    const int g = xcd_group(blockIdx.x, v.G);
+    const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
+    const int nown = 3 * (r1 - r0);
+    double* xs = dyn;
+    int* tl = reinterpret_cast<int*>(dyn + 3 * v.RG);
+    // every independent load before the first barrier
+    const double* pold = k > 1 ? v.p[(k - 1) & 1] : v.z;  // k = 1: p_1 = z_0 (+ 0 * z_0)
+    double zo[2], po[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        zo[q] = po[q] = 0.0;
+        if (o < nown) {
+            zo[q] = v.z[3LL * r0 + o];
+            po[q] = pold[3LL * r0 + o];
+        }
+    }
+    const int tb0 = v.tptr[r0], tn = v.tptr[r1] - tb0;
+    for (int e = t; e < tn; e += kThreads) tl[e] = v.tidx[tb0 + e];
+    const double rk2 = v.st->rho[k & 1];
+    // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
+    const double rk1 = sum_partials(v.P_rho[(k - 1) & 1], v.G, buf);
+    if (g == 0 && t == 0) v.st->rho[(k - 1) & 1] = rk1;
+    const double beta = k > 1 ? rk1 / rk2 : 0.0;
+    double* pk = v.p[k & 1];
+    double pv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        pv[q] = 0.0;
+        if (o < nown) {
+            pv[q] = __fma_rn(beta, po[q], zo[q]);
+            pk[3LL * r0 + o] = pv[q];
+        }
+        if (o < 3 * v.RG) xs[o] = pv[q];
+    }
+    __syncthreads();
+    double acc[2];
+    stream_sym<T>(v, H, XDir{v.z, pold, beta}, xs, tl, tb0, r0, r1, prod, acc);
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        if (o < nown) {
+            v.q[3LL * r0 + o] = acc[q];
+            part += pv[q] * acc[q];
+        }
+    }
+    part = block_sum(part, buf);
+    if (t == 0) v.P_sigma[g] = part;
+}
+
 // out = b - H x in FP64 over a group, with the partials of ||out||^2 (and
 // ||b||^2 for the initial residual) and, except for the final check, the
 // restriction of the new residual to the coarse levels.
-template <int kMode>
+template <int kMode, bool kSym>
 __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __restrict__ out) {
-    __shared__ double prod[3 * kChunk];
+    __shared__ double prod[(kSym ? 6 * kSymChunk : 3 * kChunk)];
     __shared__ double scratch[kThreads / 64];
-    extern __shared__ double dyn[];  // rs[3*RG] + restriction scratch
+    extern __shared__ double dyn[];  // rs[3*RG] + restriction scratch (+ xs[3*RG] + tl[maxT] ints)
     if (kMode == kResidReplace && v.st->done) return;
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     double acc[2];
     const GroupUnits gu = restrict_prefetch(v, g, dyn + 3 * v.RG);
-    stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, XVec{v.x}, r0, r1, prod, acc);
+    if constexpr (kSym) {
+        double* xs = dyn + 3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L);
+        int* tl = reinterpret_cast<int*>(xs + 3 * v.RG);
+        const int nown = 3 * (r1 - r0);
+        for (int o = threadIdx.x; o < 3 * v.RG; o += kThreads) xs[o] = o < nown ? v.x[3LL * r0 + o] : 0.0;
+        const int tb0 = v.tptr[r0], tn = v.tptr[r1] - tb0;
+        for (int e = threadIdx.x; e < tn; e += kThreads) tl[e] = v.tidx[tb0 + e];
+        __syncthreads();
+        stream_sym<double>(v, v.H64, XVec{v.x}, xs, tl, tb0, r0, r1, prod, acc);
+    } else {
+        stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nsb}, XVec{v.x}, r0, r1, prod, acc);
+    }
     double rr = 0.0, bb = 0.0;
     double* rs = dyn;
 #pragma unroll
@@ -207,22 +367,38 @@ hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void
 
 hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s) {
     dim3 g(v.G), b(kThreads);
-    if (f32)
+    if (v.sym) {
+        const size_t shmem = sizeof(double) * 3 * v.RG + sizeof(int) * v.maxT;
+        if (f32)
+            launch_kernel(k_spmv_pq_sym<float>, g, b, shmem, s, v, static_cast<const float*>(v.H32), k);
+        else
+            launch_kernel(k_spmv_pq_sym<double>, g, b, shmem, s, v, static_cast<const double*>(v.H64), k);
+    } else if (f32) {
         launch_kernel(k_spmv_pq<float>, g, b, 0, s, v, static_cast<const float*>(v.H32), k);
-    else
+    } else {
         launch_kernel(k_spmv_pq<double>, g, b, 0, s, v, static_cast<const double*>(v.H64), k);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_residual(const SolverView& v, int mode, double* out, hipStream_t s) {
+template <bool kSym>
+void launch_residual_t(const SolverView& v, int mode, double* out, hipStream_t s) {
     dim3 g(v.G), b(kThreads);
-    const size_t shmem = sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L));
+    size_t shmem = sizeof(double) * (3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L));
+    if (kSym) shmem += sizeof(double) * 3 * v.RG + sizeof(int) * v.maxT;
     switch (mode) {
-        case kResidInit: launch_kernel(k_residual<kResidInit>, g, b, shmem, s, v, out); break;
-        case kResidReplace: launch_kernel(k_residual<kResidReplace>, g, b, shmem, s, v, out); break;
-        case kResidConfirm: launch_kernel(k_residual<kResidConfirm>, g, b, shmem, s, v, out); break;
-        default: launch_kernel(k_residual<kResidFinal>, g, b, shmem, s, v, out); break;
+        case kResidInit: launch_kernel(k_residual<kResidInit, kSym>, g, b, shmem, s, v, out); break;
+        case kResidReplace: launch_kernel(k_residual<kResidReplace, kSym>, g, b, shmem, s, v, out); break;
+        case kResidConfirm: launch_kernel(k_residual<kResidConfirm, kSym>, g, b, shmem, s, v, out); break;
+        default: launch_kernel(k_residual<kResidFinal, kSym>, g, b, shmem, s, v, out); break;
     }
+}
+
+hipError_t launch_residual(const SolverView& v, int mode, double* out, hipStream_t s) {
+    if (v.sym)
+        launch_residual_t<true>(v, mode, out, s);
+    else
+        launch_residual_t<false>(v, mode, out, s);
     return hipGetLastError();
 }
 

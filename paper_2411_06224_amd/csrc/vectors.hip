@@ -212,7 +212,7 @@ hipError_t launch_finalize(const SolverView& v, hipStream_t s) {
 }
 
 hipError_t launch_permute_H(const SolverView& v, const double* Hu, bool f32, hipStream_t s) {
-    launch_kernel(k_permute_H, dim3(ceil_div(v.nnzb, kVecThreads)), dim3(kVecThreads), 0, s, v.nnzb, v.perm_src, Hu,
+    launch_kernel(k_permute_H, dim3(ceil_div(v.nsb, kVecThreads)), dim3(kVecThreads), 0, s, v.nsb, v.perm_src, Hu,
                        v.H64, f32 ? v.H32 : nullptr);
     return hipGetLastError();
 }

@@ -99,10 +99,13 @@ class MasPcg:
     ``MasPcg(row_ptr, col_idx, graph=None, domain_size=16, max_levels=0,
     precision="f64")`` runs the symbolic analysis on host copies of the
     pattern (numpy arrays or CPU tensors); ``graph=(g_ptr, g_adj)`` is the
-    node graph to partition (default: the pattern of H).
+    node graph to partition (default: the pattern of H).  ``partition=part``
+    (an int array of node -> level-0 domain, e.g. ``morton_partition``)
+    replaces the connectivity-aware partition.
     """
 
-    def __init__(self, row_ptr, col_idx, graph=None, domain_size=16, max_levels=0, precision="f64", poison=False):
+    def __init__(self, row_ptr, col_idx, graph=None, domain_size=16, max_levels=0, precision="f64", poison=False,
+                 partition=None):
         """``poison=True`` fills a new workspace with 0xFF bytes (NaN doubles) so
         that any read of memory the library did not write shows up."""
         self._poison = poison
@@ -125,10 +128,22 @@ class MasPcg:
             gpp, gap = gp.ctypes.data_as(ctypes.c_void_p), ga.ctypes.data_as(ctypes.c_void_p)
         else:
             gpp = gap = None
-        check(
-            "mas_analyze",
-            L.mas_analyze(h, n, ci.size, rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p), gpp, gap),
-        )
+        if partition is not None:
+            part = np.ascontiguousarray(np.asarray(partition), dtype=np.int32)
+            if part.size != n:
+                raise ValueError("partition needs one domain id per node")
+            check(
+                "mas_analyze_partition",
+                L.mas_analyze_partition(h, n, ci.size, rp.ctypes.data_as(ctypes.c_void_p),
+                                        ci.ctypes.data_as(ctypes.c_void_p), part.ctypes.data_as(ctypes.c_void_p),
+                                        int(part.max()) + 1 if part.size else 0),
+            )
+        else:
+            check(
+                "mas_analyze",
+                L.mas_analyze(h, n, ci.size, rp.ctypes.data_as(ctypes.c_void_p), ci.ctypes.data_as(ctypes.c_void_p),
+                              gpp, gap),
+            )
         self.n_rows = n
         self.nnzb = int(ci.size)
         self._ws = None
@@ -159,6 +174,7 @@ class MasPcg:
             "coarse_nnzb": list(inf.coarse_nnzb[:lv]),
             "workspace_bytes": int(inf.workspace_bytes),
             "inverse_bytes": int(inf.inverse_bytes),
+            "stored_blocks": int(inf.stored_blocks),
         }
 
     def ordering(self):

@@ -108,6 +108,7 @@ def cube_system(
         "seed": seed,
         "mesh_edges": int(edges.shape[0]),
         "contacts": int(n_contacts),
+        "positions": x,  # current node positions (V, 3)
     }
     if n_contacts:
         pairs, pool = _contact_pairs(n, edges, n_contacts, np.random.default_rng(s_pairs))

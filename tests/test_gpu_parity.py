@@ -293,6 +293,60 @@ def test_pcg_stop_at_every_iteration_count(dev, max_iter):
     assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
 
 
+@pytest.mark.parametrize("case", ["cube", "dense_local"])
+def test_pcg_storage_paths(dev, case):
+    """Group-symmetric storage of H (cube: each internal block pair kept once)
+    and the full storage it falls back to when a group's transposed entries
+    exceed the LDS list (dense local couplings): both against the oracle."""
+    _say("pcg storage path", case)
+    if case == "cube":
+        s = SYSTEMS["contact6"]()
+    else:
+        s = synth.random_spd_system(2000, 90000, seed=6, local=60)
+    P = _oracle(s, 16)
+    S = _solver(s, 16)
+    inf = S.info()
+    if case == "cube":
+        assert inf["stored_blocks"] < inf["nnzb"]
+    else:
+        assert inf["stored_blocks"] == inf["nnzb"]
+    H = _H(s, dev)
+    S.build(H)
+    xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+    x, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10)
+    assert res["iterations"] == it == 10
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+    # the final FP64 residual b - H x is computed from the stored H as well
+    true = np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, x.cpu().numpy())) / np.linalg.norm(s.b)
+    assert abs(res["true_rel_residual"] - true) <= 1e-12 * max(true, 1e-300) + 1e-15
+
+
+def test_pcg_morton_partition(dev):
+    """Level-0 domains in Morton order of the node positions (the earlier MAS
+    ordering, Sec. 3.1) through mas_analyze_partition, against the oracle
+    built from the same partition; iteration counts of both orderings are
+    printed (the ablation of Sec. 3.1)."""
+    from paper_2411_06224_amd import MasPcg, morton_partition
+
+    _say("pcg morton partition")
+    s = SYSTEMS["contact6"]()
+    part = morton_partition(s.meta["positions"], 16)
+    P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=16, part=part, M=int(part.max()) + 1)
+    S = MasPcg(s.row_ptr, s.col_idx, domain_size=16, partition=part, poison=True)
+    H = _H(s, dev)
+    S.build(H)
+    xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+    x, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10)
+    assert res["iterations"] == it == 10
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+    _, res_m = S.solve(H, _t(s.b, dev), tol=1e-6)
+    C = _solver(s, 16)
+    C.build(H)
+    _, res_c = C.solve(H, _t(s.b, dev), tol=1e-6)
+    print(f"iterations to 1e-6: connectivity ordering {res_c['iterations']}, Morton ordering {res_m['iterations']}")
+    assert res_m["status"] == 0 and res_c["status"] == 0
+
+
 def test_pcg_long_range_couplings(dev):
     """Random long-range couplings: every group touches thousands of columns
     and the hierarchy runs to the level cap."""

@@ -140,3 +140,80 @@ def test_ordering_bit_exact_large_cube():
 
     inf = _compare_with_oracle(large_cube(), 16)
     assert inf["n_rows"] == 117649 and inf["nnzb"] == 1526513
+
+
+def _morton_bruteforce(q):
+    """Bit-by-bit interleave of three 21-bit integers (x highest of each triple)."""
+    code = 0
+    for bit in range(21):
+        code |= ((int(q[0]) >> bit) & 1) << (3 * bit + 2)
+        code |= ((int(q[1]) >> bit) & 1) << (3 * bit + 1)
+        code |= ((int(q[2]) >> bit) & 1) << (3 * bit)
+    return code
+
+
+def test_morton_codes_match_bitwise_interleave():
+    from paper_2411_06224_amd import morton_codes
+
+    rng = np.random.default_rng(3)
+    pts = rng.uniform(-2.0, 5.0, size=(200, 3))
+    pts[0] = pts.min(axis=0)
+    pts[1] = pts.max(axis=0)
+    codes = morton_codes(pts)
+    lo, hi = pts.min(axis=0), pts.max(axis=0)
+    q = np.clip(np.floor((pts - lo) / (hi - lo) * ((1 << 21) - 1)).astype(np.int64), 0, (1 << 21) - 1)
+    for i in range(len(pts)):
+        assert int(codes[i]) == _morton_bruteforce(q[i])
+    # a 2x2x2 lattice orders as the Z-curve: x is the most significant bit of each triple
+    lat = np.array([[x, y, z] for x in (0.0, 1.0) for y in (0.0, 1.0) for z in (0.0, 1.0)])
+    assert list(np.argsort(morton_codes(lat))) == list(range(8))
+
+
+def test_given_partition_bit_exact_with_oracle():
+    """Morton-ordered level-0 domains (the earlier MAS ordering, Sec. 3.1)
+    through mas_analyze_partition: slots, supernodes and levels as the oracle
+    builds them from the same partition."""
+    from paper_2411_06224_amd import morton_partition
+
+    for s, N in ((small_cube(), 16), (cube(6, E=1e6, nu=0.49, seed=21, n_contacts=60), 16), (small_cube(), 4)):
+        part = morton_partition(s.meta["positions"], N)
+        M = int(part.max()) + 1
+        lib = MasPcg(s.row_ptr, s.col_idx, domain_size=N, partition=part)
+        inf = lib.info()
+        mp, rm, sn = lib.ordering()
+        P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, part=part, M=M)
+        omp, orm = P.maps()
+        assert inf["parts"] == M == P.parts
+        assert np.array_equal(mp, omp) and np.array_equal(rm, orm)
+        assert inf["levels"] == P.levels
+        for l in range(P.levels):
+            assert inf["units"][l] == P.units(l)
+            assert np.array_equal(sn[l], P.sn(l))
+        lib.close()
+
+
+def test_given_partition_rejects_invalid():
+    s = cube(2)
+    n = s.n
+    L = _lib.load()
+    opts = _lib.MasOptions(4, 0, 0, 0)
+
+    def rc(part, n_parts):
+        h = ctypes.c_void_p()
+        assert L.mas_create(ctypes.byref(opts), ctypes.byref(h)) == 0
+        p = np.ascontiguousarray(part, dtype=np.int32)
+        r = L.mas_analyze_partition(h, n, s.col_idx.size, s.row_ptr.ctypes.data_as(ctypes.c_void_p),
+                                    s.col_idx.ctypes.data_as(ctypes.c_void_p), p.ctypes.data_as(ctypes.c_void_p),
+                                    n_parts)
+        L.mas_destroy(h)
+        return r
+
+    ok = np.arange(n) // 4
+    assert rc(ok, int(ok.max()) + 1) == 0
+    assert rc(ok, int(ok.max())) == _lib.MAS_INVALID_ARG  # id out of range
+    assert rc(ok, int(ok.max()) + 2) == _lib.MAS_INVALID_ARG  # an empty part
+    big = np.arange(n) // 5  # parts of 5 > domain size 4
+    assert rc(big, int(big.max()) + 1) == _lib.MAS_INVALID_ARG
+    neg = ok.copy()
+    neg[0] = -1
+    assert rc(neg, int(ok.max()) + 1) == _lib.MAS_INVALID_ARG
