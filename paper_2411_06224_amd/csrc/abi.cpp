@@ -21,7 +21,7 @@ constexpr size_t kAlign = 256;
 
 struct Layout {
     size_t total = 0;
-    size_t remap, map, perm_src, rp0, ci0, lead1, anc, g_u1, srp, sci, srow, tptr, tidx;
+    size_t remap, map, perm_src, perm_full, rp0, ci0, lead1, anc, g_u1, srp, sci, srow, tptr, tidx;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
     size_t ganc[kMaxLv], gpos[kMaxLv], cp_ptr[kMaxLv];
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
@@ -135,6 +135,9 @@ void make_layout(mas_handle* h) {
     Y.map = Y.take(I * P.V);
     const size_t nsb = P.sym ? P.sci.size() : static_cast<size_t>(P.nnzb);
     Y.perm_src = Y.take(I * nsb);
+    // the FP32 copy of the mixed solve keeps the full storage (its SpMV is
+    // faster there), with its own permutation when the FP64 copy is symmetric
+    Y.perm_full = (mixed && P.sym) ? Y.take(I * P.nnzb) : Y.perm_src;
     Y.rp0 = Y.take(I * (P.NS + 1));
     Y.ci0 = Y.take(I * P.nnzb);
     Y.lead1 = Y.take(I * P.NS);
@@ -162,7 +165,7 @@ void make_layout(mas_handle* h) {
         }
     }
     Y.H64 = Y.take(Dd * 9 * nsb);
-    Y.H32 = mixed ? Y.take(F * 9 * nsb) : 0;
+    Y.H32 = mixed ? Y.take(F * 9 * static_cast<size_t>(P.nnzb)) : 0;
     for (int l = 1; l < P.L; ++l) Y.A[l] = Y.take(Dd * 9 * P.ciA[l].size());
     for (int l = 0; l < P.L; ++l) {
         const size_t cnt = static_cast<size_t>(P.ndom[l]) * n * n;
@@ -237,6 +240,7 @@ SolverView view(const mas_handle* h) {
     v.remap = at<int>(h, Y.remap);
     v.map = at<int>(h, Y.map);
     v.perm_src = at<int>(h, Y.perm_src);
+    v.perm_full = at<int>(h, Y.perm_full);
     v.rp0 = at<int>(h, Y.rp0);
     v.ci0 = at<int>(h, Y.ci0);
     v.lead1 = at<int>(h, Y.lead1);
@@ -293,6 +297,7 @@ int upload_plan(mas_handle* h, hipStream_t s) {
     HIP_TRY(put(Y.remap, P.remap));
     HIP_TRY(put(Y.map, P.map));
     HIP_TRY(put(Y.perm_src, P.sym ? P.sperm : P.perm_src));
+    if (Y.perm_full != Y.perm_src) HIP_TRY(put(Y.perm_full, P.perm_src));
     if (P.sym) {
         HIP_TRY(put(Y.srp, P.srp));
         HIP_TRY(put(Y.sci, P.sci));

@@ -34,7 +34,8 @@ void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t 
 struct SolverView {
     int V, N, M, NS, L, nnzb;
     int D0, RG, G;  // work groups: D0 level-0 domains = RG slots; G groups
-    int sym;        // 1: H64 / H32 hold the group-symmetric storage (nsb blocks), 0: full slot-ordered H
+    int sym;        // 1: H64 holds the group-symmetric storage (nsb blocks), 0: the full slot-ordered H;
+                    // H32 (mixed) always holds the full storage (nnzb blocks)
     int nsb;        // blocks of the stored slot-ordered H (H64 / H32 planes)
     int maxT;       // most transposed entries of one group (symmetric storage)
     int units[kMaxLv];
@@ -42,7 +43,8 @@ struct SolverView {
     // plans
     const int* remap;     // [NS]
     const int* map;       // [V]
-    const int* perm_src;  // [nsb] caller block of each stored block
+    const int* perm_src;  // [nsb] caller block of each stored block (H64)
+    const int* perm_full; // [nnzb] caller block of each full slot-ordered block (H32: full storage)
     const int* srp;       // symmetric storage: [NS+1] stored rows
     const int* sci;       // [nsb] column slot of each stored block
     const uint8_t* srow;  // [nsb] local row (slot - group start) of each stored block
@@ -57,7 +59,7 @@ struct SolverView {
     const int* ganc[kMaxLv];      // l >= 2: [G * W1] level-l unit of each level-1 unit of each group (-1 pad)
     const int* gpos[kMaxLv];      // l >= 2: [G * W1] its partial position, -1 if it writes none
     const int* cp_ptr[kMaxLv];    // l >= 2: [S_l + 1]
-    // stored slot-ordered matrix (9 planes of nsb values)
+    // stored slot-ordered matrix (9 planes: H64 of nsb, H32 of nnzb values)
     double* H64;
     float* H32;
     // inverses per level, column-major (3N)^2 per domain

@@ -10,13 +10,14 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Inverse entries in the apply.  FP64 inverses (136 MB at the 48^3 cube) do
-// not fit the 256 MB MALL next to H, so they are streamed with non-temporal
-// loads that leave the caches to H and the vectors; the FP32 set of the mixed
-// solve fits and is read through the caches.
-template <typename TI>
+// Inverse entries in the apply.  The level-0 FP64 inverses (136 MB at the
+// 48^3 cube) do not fit the 256 MB MALL next to H, so they are streamed with
+// non-temporal loads that leave the caches to H, the vectors and the coarse
+// inverses (kStream); the FP32 set of the mixed solve fits and is read
+// through the caches, as are the coarse levels (16 MB).
+template <typename TI, bool kStream = true>
 __device__ __forceinline__ double inv_load(const TI* p) {
-    if constexpr (sizeof(TI) == 8)
+    if constexpr (sizeof(TI) == 8 && kStream)
         return __builtin_nontemporal_load(p);
     else
         return static_cast<double>(*p);
@@ -321,7 +322,7 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
 #pragma unroll
             for (int j = 0; j < kCols; ++j) {
                 const int kk = ppart * kCols + j;
-                pre[j] = kk < n ? inv_load(inv + static_cast<long long>(kk) * n + prow) : 0.0;
+                pre[j] = kk < n ? inv_load<TI, false>(inv + static_cast<long long>(kk) * n + prow) : 0.0;
             }
         }
     }
@@ -397,7 +398,7 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
     } else if (t < n) {
         double acc = 0.0;
 #pragma unroll 8
-        for (int kk = 0; kk < n; ++kk) acc += inv_load(inv + static_cast<long long>(kk) * n + t) * rl[kk];
+        for (int kk = 0; kk < n; ++kk) acc += inv_load<TI, false>(inv + static_cast<long long>(kk) * n + t) * rl[kk];
         v.y[l][3 * u0 + t] = acc;
     }
 }

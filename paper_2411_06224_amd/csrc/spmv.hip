@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     }
     const XDir dir{v.z, pold, beta};
     double acc[2];
-    stream_rows<T, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nsb}, dir, r0, r1, prod, acc);
+    stream_rows<T, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, dir, r0, r1, prod, acc);
     double* pk = v.p[k & 1];
     double part = 0.0;
 #pragma unroll
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
         __syncthreads();
         stream_sym<double>(v, v.H64, XVec{v.x}, xs, tl, tb0, r0, r1, prod, acc);
     } else {
-        stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nsb}, XVec{v.x}, r0, r1, prod, acc);
+        stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, XVec{v.x}, r0, r1, prod, acc);
     }
     double rr = 0.0, bb = 0.0;
     double* rs = dyn;
@@ -367,12 +367,9 @@ hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void
 
 hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s) {
     dim3 g(v.G), b(kThreads);
-    if (v.sym) {
+    if (v.sym && !f32) {
         const size_t shmem = sizeof(double) * 3 * v.RG + sizeof(int) * v.maxT;
-        if (f32)
-            launch_kernel(k_spmv_pq_sym<float>, g, b, shmem, s, v, static_cast<const float*>(v.H32), k);
-        else
-            launch_kernel(k_spmv_pq_sym<double>, g, b, shmem, s, v, static_cast<const double*>(v.H64), k);
+        launch_kernel(k_spmv_pq_sym<double>, g, b, shmem, s, v, static_cast<const double*>(v.H64), k);
     } else if (f32) {
         launch_kernel(k_spmv_pq<float>, g, b, 0, s, v, static_cast<const float*>(v.H32), k);
     } else {

@@ -47,8 +47,10 @@ __global__ void __launch_bounds__(kVecThreads) k_permute_H(int nnzb, const int* 
     double val[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) val[c] = blk[c];
+    if (H64) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) H64[(long long)c * nnzb + k] = val[c];
+        for (int c = 0; c < 9; ++c) H64[(long long)c * nnzb + k] = val[c];
+    }
     if (H32) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) H32[(long long)c * nnzb + k] = static_cast<float>(val[c]);
@@ -212,8 +214,15 @@ hipError_t launch_finalize(const SolverView& v, hipStream_t s) {
 }
 
 hipError_t launch_permute_H(const SolverView& v, const double* Hu, bool f32, hipStream_t s) {
-    launch_kernel(k_permute_H, dim3(ceil_div(v.nsb, kVecThreads)), dim3(kVecThreads), 0, s, v.nsb, v.perm_src, Hu,
-                       v.H64, f32 ? v.H32 : nullptr);
+    if (!v.sym || !f32) {
+        launch_kernel(k_permute_H, dim3(ceil_div(v.nsb, kVecThreads)), dim3(kVecThreads), 0, s, v.nsb, v.perm_src, Hu,
+                      v.H64, f32 ? v.H32 : nullptr);
+    } else {  // symmetric FP64 copy, full FP32 copy
+        launch_kernel(k_permute_H, dim3(ceil_div(v.nsb, kVecThreads)), dim3(kVecThreads), 0, s, v.nsb, v.perm_src, Hu,
+                      v.H64, static_cast<float*>(nullptr));
+        launch_kernel(k_permute_H, dim3(ceil_div(v.nnzb, kVecThreads)), dim3(kVecThreads), 0, s, v.nnzb, v.perm_full,
+                      Hu, static_cast<double*>(nullptr), v.H32);
+    }
     return hipGetLastError();
 }
 
