@@ -256,7 +256,7 @@ def main():
         log(f"mixed solve: {ms_mixed:.3f} ms, {mres['iterations']} its, true res {mres['true_rel_residual']:.3e}")
         msolver.close()
 
-        # ordering ablation (Sec. 3.1): level-0 domains of consecutive nodes in
+        # ordering ablation (Sec. 4.1): level-0 domains of consecutive nodes in
         # Morton order of the positions instead of the connectivity-aware
         # partition; same hierarchy construction, same solver
         t0 = time.perf_counter()

@@ -11,8 +11,8 @@
  *     M^-1 = sum_l C_l^T blockdiag_d( (S_d C_l H C_l^T S_d^T)^-1 ) C_l
  *
  * (Supp. Eq. 4-6; domains from a connectivity-aware partition with padding,
- * Sec. 3.2 and Fig. mapping; coarse levels from connected components inside
- * each domain, Sec. 3.1 and Supp. Alg. 2-5; per-domain matrices from the
+ * Sec. 4.2 and Fig. mapping; coarse levels from connected components inside
+ * each domain, Sec. 4.1 and Supp. Alg. 2-5; per-domain matrices from the
  * algorithm "Compute MAS preconditioner" and inverted over unpadded lanes).
  *
  * Conventions
@@ -125,7 +125,7 @@ int mas_create(const mas_options* opts, mas_handle** out);
 void mas_destroy(mas_handle* h);
 
 /* Symbolic phase, on the host, once per sparsity pattern (the paper runs its
- * METIS reordering once at load, Sec. 3.2): partition of the node graph into
+ * METIS reordering once at load, Sec. 4.2): partition of the node graph into
  * M = ceil(V/(N - N_o)) parts of at most N nodes with the smallest slack N_o
  * (Eq. num_subdomains), map/remap with -1 padding, supernode hierarchy from
  * the block pattern of H (contact couplings included), and every gather /
@@ -142,7 +142,7 @@ int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_
 /* mas_analyze with a caller-given level-0 partition instead of the
  * connectivity-aware bisection, e.g. consecutive nodes in Morton (Z-order)
  * of their positions, the domain ordering of the earlier MAS preconditioner
- * that Sec. 3.1 compares against.  part[n_rows] (host) puts node i in
+ * that Sec. 4.1 compares against.  part[n_rows] (host) puts node i in
  * level-0 domain part[i], 0 <= part[i] < n_parts; every domain must hold
  * 1..domain_size nodes.  Slots, hierarchy and plans then follow as in
  * mas_analyze (slack reported as 0).

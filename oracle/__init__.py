@@ -77,6 +77,8 @@ def lib():
         L.orc_spmv.argtypes = [_i, _pi, _pi, _pd, _pd, _pd]
         L.orc_pcg.argtypes = [_i, _pi, _pi, _pd, _vp, _pd, _pd, _d, _i, _pi, _pd, _pd]
         L.orc_adjoint_scatter.argtypes = [_i, _pi, _pi, _pd, _pd, _pd]
+        L.orc_assemble.argtypes = [_i, ctypes.c_long, _pi, _pi, _pd, _pi, _pi, _pd]
+        L.orc_assemble.restype = ctypes.c_long
         _lib = L
     return _lib
 
@@ -134,6 +136,23 @@ def adjoint_scatter(row_ptr, col_idx, lam, x):
     out = np.empty((ci.size, 3, 3))
     lib().orc_adjoint_scatter(n, rpp, cip, lp, xp, out.ctypes.data_as(_pd))
     return out
+
+
+def assemble(n, rows, cols, blocks):
+    """BCSR (row_ptr, col_idx, val[nnzb, 3, 3]) of a block list: equal
+    (row, col) blocks summed in list order."""
+    r, rp = _ci(rows)
+    c, cp = _ci(cols)
+    b, bp = _cd(np.asarray(blocks, dtype=np.float64).reshape(-1))
+    m = r.size
+    row_ptr = np.zeros(n + 1, dtype=np.int32)
+    col_idx = np.zeros(max(m, 1), dtype=np.int32)
+    val = np.zeros((max(m, 1), 3, 3))
+    nb = lib().orc_assemble(int(n), m, rp, cp, bp, row_ptr.ctypes.data_as(_pi), col_idx.ctypes.data_as(_pi),
+                            val.ctypes.data_as(_pd))
+    if nb < 0:
+        raise ValueError("block index out of range")
+    return row_ptr, col_idx[:nb], val[:nb]
 
 
 class MAS:

@@ -4,7 +4,7 @@
  *
  * Readings of points the paper leaves open (each also listed in the design
  * notes of the repository):
- *  - Partitioner (Sec. 3.2 uses METIS, unavailable here): recursive BFS
+ *  - Partitioner (Sec. 4.2 uses METIS, unavailable here): recursive BFS
  *    bisection.  RB(S, k): k == 1 emits S as the next part; otherwise
  *    kL = k/2, kR = k - kL, nL = floor(|S| kL / k), order = BFS_ORDER(S),
  *    RB(order[0:nL], kL), RB(order[nL:], kR).  BFS_ORDER on the subgraph
@@ -16,7 +16,7 @@
  *    of the same domain are connected when a stored block (i, j), i != j,
  *    has sn_l(i) = s, sn_l(j) = t.  Components are the next level's
  *    supernodes, numbered per domain by lowest lane, domains in order
- *    (Sec. 3.1 case-study figure: a merged supernode takes the position of
+ *    (Sec. 4.1 case-study figure: a merged supernode takes the position of
  *    its lowest member; Supp. Alg. 5 elects the lowest lane).  Stop when a
  *    level has one domain, max_levels is reached or nothing merged.
  *  - Coarse weights: unit 3x3 identities (plain sums of blocks).
@@ -605,4 +605,48 @@ void orc_adjoint_scatter(int n, const int* rp, const int* ci, const double* lamb
             for (int r = 0; r < 3; ++r)
                 for (int c = 0; c < 3; ++c) dLdH[(size_t)p * 9 + 3 * r + c] = -lambda[3 * i + r] * x[3 * j + c];
         }
+}
+
+/* ------------------------------------------------------------- assembly */
+
+typedef struct {
+    int row, col;
+    long idx;
+} orc_entry;
+
+static int orc_entry_cmp(const void* a, const void* b) {
+    const orc_entry* x = (const orc_entry*)a;
+    const orc_entry* y = (const orc_entry*)b;
+    if (x->row != y->row) return x->row < y->row ? -1 : 1;
+    if (x->col != y->col) return x->col < y->col ? -1 : 1;
+    if (x->idx != y->idx) return x->idx < y->idx ? -1 : 1;
+    return 0;
+}
+
+long orc_assemble(int n, long n_in, const int* rows, const int* cols, const double* blocks, int* row_ptr,
+                  int* col_idx, double* val) {
+    for (long k = 0; k < n_in; ++k)
+        if (rows[k] < 0 || rows[k] >= n || cols[k] < 0 || cols[k] >= n) return -1;
+    orc_entry* e = (orc_entry*)malloc(sizeof(orc_entry) * (size_t)(n_in > 0 ? n_in : 1));
+    for (long k = 0; k < n_in; ++k) {
+        e[k].row = rows[k];
+        e[k].col = cols[k];
+        e[k].idx = k;
+    }
+    /* order by (row, col, position in the list): equal blocks meet in list order */
+    qsort(e, (size_t)n_in, sizeof(orc_entry), orc_entry_cmp);
+    long nb = 0;
+    for (int i = 0; i <= n; ++i) row_ptr[i] = 0;
+    for (long k = 0; k < n_in; ++k) {
+        if (k == 0 || e[k].row != e[k - 1].row || e[k].col != e[k - 1].col) {
+            col_idx[nb] = e[k].col;
+            for (int c = 0; c < 9; ++c) val[9 * nb + c] = 0.0;
+            row_ptr[e[k].row + 1]++;
+            ++nb;
+        }
+        for (int c = 0; c < 9; ++c) val[9 * (nb - 1) + c] += blocks[9 * e[k].idx + c];
+    }
+    for (int i = 0; i < n; ++i) row_ptr[i + 1] += row_ptr[i];
+    free(e);
+    return nb;
 }

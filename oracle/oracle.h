@@ -9,20 +9,23 @@
  *
  * What it computes (StiffGIPC, arXiv 2411.06224):
  *   - partition of the node graph into M = ceil(V / (N - N_o)) parts of at
- *     most N nodes, smallest slack N_o first (Sec. 3.2, Eq. num_subdomains);
+ *     most N nodes, smallest slack N_o first (Sec. 4.2, Eq. num_subdomains);
  *     METIS is replaced by a specified recursive BFS bisection (see below);
- *   - map / remap with -1 padding, one part per level-0 domain (Sec. 3.2,
+ *   - map / remap with -1 padding, one part per level-0 domain (Sec. 4.2,
  *     Fig. mapping; Supp. Alg. 1 map/remap construction);
  *   - the supernode hierarchy: connected components inside each domain,
  *     numbered by their lowest lane, N consecutive supernodes per coarser
- *     domain (Sec. 3.1 case study, Supp. Alg. 2-5 semantics);
+ *     domain (Sec. 4.1 case study, Supp. Alg. 2-5 semantics);
  *   - per level and domain the matrix S_d C_l H C_l^T S_d^T and its inverse
  *     over occupied lanes (Alg. "Compute MAS preconditioner"; Supp. Eq. 5);
  *   - the MAS operator  z = sum_l C_l^T blockdiag_d(Inv_{l,d}) C_l r
  *     (Supp. Eq. 4-6);
  *   - 3x3-block CSR SpMV, textbook PCG (Sec. 3.2 "IP Minimization and Linear
  *     Solves": P d = -grad E solved by PCG) and the adjoint block scatter
- *     dL/dH_ij = -lambda_i x_j^T.
+ *     dL/dH_ij = -lambda_i x_j^T;
+ *   - assembly of a list of 3x3 blocks into BCSR, equal (row, col) blocks
+ *     summed in list order (what the hash-based reduction of Sec. 6.2
+ *     produces).
  *
  * Conventions.  H is 3x3-block CSR: row_ptr[n+1], col_idx[nnzb] ascending per
  * row, val[nnzb*9] row-major blocks; both triangles stored.  Vectors are
@@ -76,6 +79,15 @@ int orc_pcg(int n, const int* rp, const int* ci, const double* val, const orc_ma
             double* x, double tol, int max_iter, int* iters, double* relres, double* true_relres);
 void orc_adjoint_scatter(int n, const int* rp, const int* ci, const double* lambda, const double* x,
                          double* dLdH);
+
+/* Assembly of 3x3 blocks given as a list (row[k], col[k], blocks[9k..9k+8],
+ * row-major) into BCSR (the hash-based reduction of Sec. 6.2 computes the
+ * same sums): blocks with the same (row, col) are added in list order, rows
+ * ascending, columns ascending within a row.  row_ptr[n+1]; col_idx and val
+ * hold up to n_in blocks.  Returns the number of distinct blocks, or -1 if
+ * an index is out of range. */
+long orc_assemble(int n, long n_in, const int* rows, const int* cols, const double* blocks, int* row_ptr,
+                  int* col_idx, double* val);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,6 @@
 // MAS preconditioner on the device: coarse matrices, batched domain
 // inversion and the apply (Supp. Eq. 4-6; algorithm "Compute MAS
-// preconditioner" in Sec. 3.3).
+// preconditioner" in Sec. 4.3).
 #include <algorithm>
 
 #include "launch.hpp"

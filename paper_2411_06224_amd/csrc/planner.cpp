@@ -1,6 +1,6 @@
 // Host-side symbolic analysis (see planner.hpp).
 //
-// Ordering (Sec. 3.2): the node graph is partitioned into
+// Ordering (Sec. 4.2): the node graph is partitioned into
 // M = ceil(V / (N - N_o)) parts of at most N nodes, the slack N_o searched
 // upward from 0 (Eq. num_subdomains).  The paper uses METIS; here the
 // partitioner is a recursive BFS bisection with fully specified tie-breaks
@@ -13,7 +13,7 @@
 // Part p occupies slots [pN, pN + N) in ascending node order; the rest of
 // its slots are padding (-1), one part per MAS domain (Fig. mapping).
 //
-// Hierarchy (Sec. 3.1, Supp. Alg. 2-5): at each level the units of a domain
+// Hierarchy (Sec. 4.1, Supp. Alg. 2-5): at each level the units of a domain
 // that are coupled by stored blocks form connected components; each
 // component is a supernode of the next level, numbered inside its domain by
 // its lowest lane and globally by domain order.  N consecutive supernodes

@@ -1,6 +1,6 @@
 // Host-side symbolic analysis for the MAS preconditioner: ordering, hierarchy
 // and every gather / reduction plan the device phases consume.  Runs once per
-// sparsity pattern (the paper reorders once at load, Sec. 3.2).
+// sparsity pattern (the paper reorders once at load, Sec. 4.2).
 #pragma once
 
 #include <cstdint>

@@ -28,7 +28,7 @@ def morton_codes(positions):
 def morton_partition(positions, domain_size=16):
     """Level-0 domains of ``domain_size`` consecutive nodes in Morton order of
     their positions (ties by node id): the domain ordering of the earlier MAS
-    preconditioner that the connectivity-aware partition replaces (Sec. 3.1).
+    preconditioner that the connectivity-aware partition replaces (Sec. 4.1).
     Returns part[V] for ``MasPcg(partition=...)`` / mas_analyze_partition."""
     codes = morton_codes(positions)
     order = np.lexsort((np.arange(codes.size), codes))

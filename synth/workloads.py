@@ -70,6 +70,7 @@ def cube_system(
     noise=0.1,
     n_contacts=0,
     seed=0,
+    keep_blocks=False,
 ):
     ss = np.random.SeedSequence(seed)
     s_noise, s_rhs, s_pairs, s_q = ss.spawn(4)
@@ -121,9 +122,10 @@ def cube_system(
                 parts_c.append(pairs[:, v])
                 parts_b.append(cb[:, u, v])
         meta["contact_pool"] = int(pool)
-    row_ptr, col_idx, val = assemble_bcsr(
-        V, np.concatenate(parts_r), np.concatenate(parts_c), np.concatenate(parts_b)
-    )
+    all_r, all_c, all_b = np.concatenate(parts_r), np.concatenate(parts_c), np.concatenate(parts_b)
+    row_ptr, col_idx, val = assemble_bcsr(V, all_r, all_c, all_b)
+    if keep_blocks:  # the unassembled block list (row, col, 3x3), in generation order
+        meta["blocks"] = (all_r.astype(np.int32), all_c.astype(np.int32), all_b)
     gptr, gadj = graph_from_edges(V, edges)
     b = np.random.default_rng(s_rhs).standard_normal(3 * V)
     meta["nnzb"] = int(col_idx.size)
@@ -139,9 +141,9 @@ def config_small(seed=1000):
     return cube_system(8, 1e5, 0.4, seed=seed)
 
 
-def config_large(E=1e6, seed=1001, n_contacts=20000):
+def config_large(E=1e6, seed=1001, n_contacts=20000, keep_blocks=False):
     """48^3 cube, nu = 0.49, given E, 20,000 contact-like pairs."""
-    return cube_system(48, E, 0.49, n_contacts=n_contacts, seed=seed)
+    return cube_system(48, E, 0.49, n_contacts=n_contacts, seed=seed, keep_blocks=keep_blocks)
 
 
 WORKLOADS = {

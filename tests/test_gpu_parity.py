@@ -323,9 +323,9 @@ def test_pcg_storage_paths(dev, case):
 
 def test_pcg_morton_partition(dev):
     """Level-0 domains in Morton order of the node positions (the earlier MAS
-    ordering, Sec. 3.1) through mas_analyze_partition, against the oracle
+    ordering, Sec. 4.1) through mas_analyze_partition, against the oracle
     built from the same partition; iteration counts of both orderings are
-    printed (the ablation of Sec. 3.1)."""
+    printed (the ablation of Sec. 4.1)."""
     from paper_2411_06224_amd import MasPcg, morton_partition
 
     _say("pcg morton partition")

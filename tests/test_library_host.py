@@ -170,7 +170,7 @@ def test_morton_codes_match_bitwise_interleave():
 
 
 def test_given_partition_bit_exact_with_oracle():
-    """Morton-ordered level-0 domains (the earlier MAS ordering, Sec. 3.1)
+    """Morton-ordered level-0 domains (the earlier MAS ordering, Sec. 4.1)
     through mas_analyze_partition: slots, supernodes and levels as the oracle
     builds them from the same partition."""
     from paper_2411_06224_amd import morton_partition

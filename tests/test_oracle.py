@@ -426,3 +426,58 @@ def test_adjoint_gradient_matches_central_differences():
         fd = (loss(H + eps * dH) - loss(H - eps * dH)) / (2 * eps)
         pred = np.sum(G[p] * D) + (np.sum(G[pos[(j, i)]] * D.T) if i != j else 0.0)
         assert abs(fd - pred) <= 1e-5 * max(abs(fd), 1e-12)
+
+
+# ------------------------------------------------------------- assembly ---
+
+
+def test_assemble_integer_blocks_match_dense_accumulation():
+    """Integer-valued blocks sum exactly in any order: the assembled matrix
+    equals a dense np.add.at accumulation, the pattern is the set of keys."""
+    rng = np.random.default_rng(8)
+    n, m = 40, 3000
+    rows = rng.integers(0, n, m)
+    cols = rng.integers(0, n, m)
+    rows[:5] = 7  # a row with many duplicates
+    cols[:5] = 3
+    blocks = rng.integers(-50, 50, (m, 3, 3)).astype(np.float64)
+    rp, ci, val = oracle.assemble(n, rows, cols, blocks)
+    dense = np.zeros((3 * n, 3 * n))
+    for k in range(m):
+        dense[3 * rows[k]:3 * rows[k] + 3, 3 * cols[k]:3 * cols[k] + 3] += blocks[k]
+    keys = sorted(set(zip(rows.tolist(), cols.tolist())))
+    assert rp[-1] == len(keys) == ci.size
+    got = np.zeros_like(dense)
+    for i in range(n):
+        assert list(ci[rp[i]:rp[i + 1]]) == sorted(c for (r, c) in keys if r == i)
+        for p in range(rp[i], rp[i + 1]):
+            got[3 * i:3 * i + 3, 3 * ci[p]:3 * ci[p] + 3] = val[p]
+    assert np.array_equal(got, dense)
+
+
+def test_assemble_sums_in_list_order_and_edge_cases():
+    big = np.full((3, 3), 1e16)
+    one = np.ones((3, 3))
+    # (1e16 + 1) - 1e16 = 0 in FP64; (1e16 - 1e16) + 1 = 1
+    _, _, v = oracle.assemble(2, [1, 1, 1], [0, 0, 0], np.stack([big, one, -big]))
+    assert np.all(v[0] == 0.0)
+    _, _, v = oracle.assemble(2, [1, 1, 1], [0, 0, 0], np.stack([big, -big, one]))
+    assert np.all(v[0] == 1.0)
+    rp, ci, v = oracle.assemble(5, [], [], np.zeros((0, 3, 3)))
+    assert list(rp) == [0] * 6 and ci.size == 0
+    rp, ci, v = oracle.assemble(5, [4, 0], [1, 2], np.stack([one, 2 * one]))
+    assert list(rp) == [0, 1, 1, 1, 1, 2] and list(ci) == [2, 1]
+    with pytest.raises(ValueError):
+        oracle.assemble(3, [0, 3], [0, 0], np.stack([one, one]))
+
+
+def test_assemble_reproduces_generated_cube():
+    """The tet cube's element, mass and contact blocks reassembled: same
+    pattern as the generator's (independent numpy) assembly, values equal to
+    rounding (the generator adds with a different summation order and
+    mirrors its upper triangle)."""
+    s = synth.cube_system(4, 1e5, 0.45, seed=3, n_contacts=20, keep_blocks=True)
+    rows, cols, blocks = s.meta["blocks"]
+    rp, ci, val = oracle.assemble(s.n, rows, cols, blocks)
+    assert np.array_equal(rp, s.row_ptr) and np.array_equal(ci, s.col_idx)
+    assert np.allclose(val, s.val, rtol=1e-12, atol=1e-12 * np.abs(s.val).max())
