@@ -133,7 +133,7 @@ def main():
         del src, dst
 
     t0 = time.time()
-    s = synth.config_large(E=args.E)
+    s = synth.config_large(E=args.E, keep_blocks=not args.no_extras)
     log(f"workload generated in {time.time() - t0:.1f}s: {s.n} nodes, {s.nnzb} blocks")
     H = mp.BlockMatrix.from_numpy(s.row_ptr, s.col_idx, s.val, device=dev)
     b = torch.as_tensor(s.b, device=dev)
@@ -255,6 +255,33 @@ def main():
         }
         log(f"mixed solve: {ms_mixed:.3f} ms, {mres['iterations']} its, true res {mres['true_rel_residual']:.3e}")
         msolver.close()
+
+        # assembly of the system from its unassembled block list (element,
+        # mass and contact blocks), the step before the solve (Sec. 6.2)
+        rows_np, cols_np, blocks_np = s.meta["blocks"]
+        arows = torch.as_tensor(rows_np, device=dev)
+        acols = torch.as_tensor(cols_np, device=dev)
+        ablocks = torch.as_tensor(blocks_np.reshape(-1, 3, 3), device=dev)
+        Ha = mp.bcsr_assemble(s.n, arows, acols, ablocks)
+        same = bool(torch.equal(Ha.col_idx.cpu(), torch.as_tensor(s.col_idx.astype(np.int32))))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Ha = mp.bcsr_assemble(s.n, arows, acols, ablocks, capacity=s.nnzb)
+        torch.cuda.synchronize()
+        ms_asm = 1e3 * (time.perf_counter() - t0) / args.steps
+        m_in = int(rows_np.size)
+        asm_bytes = m_in * (72 + 8) + s.nnzb * (72 + 4) + 4 * (s.n + 1)
+        out["assembly"] = {
+            "ms": round(ms_asm, 4),
+            "blocks_in": m_in,
+            "blocks_out": int(Ha.nnzb),
+            "pattern_matches_generator": same,
+            "alg_bytes": asm_bytes,
+            "GBs": round(asm_bytes / (ms_asm * 1e-3) / 1e9, 1),
+        }
+        log(f"assembly: {m_in} blocks -> {Ha.nnzb} in {ms_asm:.3f} ms")
+        del arows, acols, ablocks, Ha
 
         # ordering ablation (Sec. 4.1): level-0 domains of consecutive nodes in
         # Morton order of the positions instead of the connectivity-aware

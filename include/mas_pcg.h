@@ -205,6 +205,31 @@ int pcg_solve(mas_handle* h, const mas_bcsr* H, const double* b, double* x, cons
 int pcg_adjoint(mas_handle* h, const mas_bcsr* H, const double* x, const double* dLdx, double* lambda, void* dLdH,
                 int32_t dLdH_dtype, const pcg_options* opts, pcg_result* res, void* stream);
 
+/* Device bytes of scratch bcsr_assemble needs for n_rows block rows and a
+ * list of n_in blocks. */
+size_t bcsr_assemble_workspace_size(int32_t n_rows, int64_t n_in);
+
+/* Assembles a list of 3x3 blocks into 3x3-block CSR on the device: the
+ * operation the hash-based parallel reduction of Sec. 6.2 performs (blocks
+ * with the same (row, col) summed; rows ascending, columns ascending within
+ * a row), here deterministic: equal blocks are summed in list order, so the
+ * result is that of a sequential pass over the list.
+ *   rows, cols: device int32[n_in], 0 <= index < n_rows.
+ *   blocks: device double[9 n_in], row-major 3x3 blocks.
+ *   row_ptr: device int32[n_rows + 1]; col_idx: device int32[capacity];
+ *   val: device double[9 capacity]  (outputs, caller-owned).
+ *   nnzb: host, receives the number of distinct blocks (also when it
+ *         exceeds capacity, so the caller can size the outputs).
+ *   workspace: device scratch of ws_bytes >= bcsr_assemble_workspace_size,
+ *              256-byte aligned.
+ * Limits: n_in < 2^31, n_rows + 1 <= 2^20, at most 4096 listed blocks per
+ * row.  Synchronises the stream.  Errors: MAS_INVALID_ARG (an index out of
+ * range, a limit exceeded, nnzb > capacity: then col_idx and val are not
+ * written), MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
+int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
+                  int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb,
+                  void* workspace, size_t ws_bytes, void* stream);
+
 /* Host copy of the handle's static description (after mas_analyze). */
 int mas_get_info(const mas_handle* h, mas_info* out);
 

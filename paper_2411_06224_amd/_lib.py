@@ -32,6 +32,8 @@ SYMBOLS = (
     "mas_build",
     "mas_apply",
     "bcsr_spmv",
+    "bcsr_assemble_workspace_size",
+    "bcsr_assemble",
     "pcg_solve",
     "pcg_adjoint",
     "mas_get_info",
@@ -135,6 +137,11 @@ def load():
     L.mas_apply.restype = ctypes.c_int
     L.bcsr_spmv.argtypes = [P(MasBcsr), vp, vp, vp]
     L.bcsr_spmv.restype = ctypes.c_int
+    L.bcsr_assemble_workspace_size.argtypes = [i32, ctypes.c_int64]
+    L.bcsr_assemble_workspace_size.restype = ctypes.c_size_t
+    L.bcsr_assemble.argtypes = [i32, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_int64, P(ctypes.c_int64), vp,
+                                ctypes.c_size_t, vp]
+    L.bcsr_assemble.restype = ctypes.c_int
     L.pcg_solve.argtypes = [vp, P(MasBcsr), vp, vp, P(PcgOptions), P(PcgResult), vp]
     L.pcg_solve.restype = ctypes.c_int
     L.pcg_adjoint.argtypes = [vp, P(MasBcsr), vp, vp, vp, vp, i32, P(PcgOptions), P(PcgResult), vp]

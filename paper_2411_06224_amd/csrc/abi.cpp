@@ -627,6 +627,38 @@ int pcg_adjoint(mas_handle* h, const mas_bcsr* H, const double* x, const double*
     return rc;
 }
 
+size_t bcsr_assemble_workspace_size(int32_t n_rows, int64_t n_in) {
+    if (n_rows < 1 || n_in < 0) return 0;
+    size_t total = 0;
+    assemble_layout(nullptr, n_rows, n_in, &total);
+    return total;
+}
+
+int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
+                  int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb,
+                  void* workspace, size_t ws_bytes, void* stream) {
+    if (n_rows < 1 || n_rows + 1 > (1 << 20) || n_in < 0 || n_in > 0x7fffffffLL || capacity < 0 || !nnzb ||
+        !row_ptr || !workspace)
+        return MAS_INVALID_ARG;
+    if (n_in > 0 && (!rows || !cols || !blocks)) return MAS_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < bcsr_assemble_workspace_size(n_rows, n_in)) return MAS_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const AsmLayout L = assemble_layout(static_cast<char*>(workspace), n_rows, n_in, nullptr);
+    HIP_TRY(launch_assemble_count(L, n_rows, n_in, rows, cols, s));
+    HIP_TRY(launch_scan(L.ucnt, n_rows, row_ptr, L.totals, s));
+    int host[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(host, L.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(host + 2, row_ptr + n_rows, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (host[0]) return MAS_INVALID_ARG;  // index out of range / row over the limit
+    *nnzb = host[2];
+    if (host[2] > capacity || (host[2] > 0 && (!col_idx || !val))) return MAS_INVALID_ARG;
+    HIP_TRY(launch_assemble_reduce(L, n_rows, blocks, row_ptr, col_idx, val, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAS_OK;
+}
+
 int mas_get_info(const mas_handle* h, mas_info* out) {
     if (!h || !out) return MAS_INVALID_ARG;
     if (!h->analyzed) return MAS_NOT_READY;

@@ -136,4 +136,21 @@ hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, int k, d
                                bool rr_true, hipStream_t s);
 hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, hipStream_t s);
 
+// assemble.hip: block-list assembly (scratch in the caller's workspace).
+struct AsmLayout {
+    int *cnt, *start, *ucnt, *perm, *scol, *totals, *flag;
+};
+// Layout of the assembly scratch from ws (ws = nullptr: sizes only; *total
+// receives the bytes needed).
+AsmLayout assemble_layout(char* ws, int n_rows, long long n_in, size_t* total);
+// Exclusive scan of n ints into out[0..n] (out[n] = total); n + 1 <= 2^20.
+hipError_t launch_scan(const int* in, int n, int* out, int* totals, hipStream_t s);
+// Counts, scatters and sorts the listed blocks per row; flag bit 0: index
+// out of range, bit 1: a row with more than 4096 listed blocks.
+hipError_t launch_assemble_count(const AsmLayout& L, int n_rows, long long n_in, const int* rows, const int* cols,
+                                 hipStream_t s);
+// Sums every (row, col) segment in list order into row_ptr / col_idx / val.
+hipError_t launch_assemble_reduce(const AsmLayout& L, int n_rows, const double* blocks, int* row_ptr, int* col_idx,
+                                  double* val, hipStream_t s);
+
 }  // namespace maspcg

@@ -14,6 +14,7 @@ from . import _lib
 from ._lib import (
     MAS_F32,
     MAS_F64,
+    MAS_INVALID_ARG,
     MAS_NOT_CONVERGED,
     MAS_OK,
     MAS_PRECISION_F64,
@@ -22,6 +23,7 @@ from ._lib import (
     MasInfo,
     MasOptions,
     PcgOptions,
+    MasError,
     PcgResult,
     check,
 )
@@ -91,6 +93,38 @@ def bcsr_spmv(H, x, out=None):
     h = H.c_struct()
     check("bcsr_spmv", L.bcsr_spmv(ctypes.byref(h), _ptr(x), _ptr(y), _stream()))
     return y
+
+
+def bcsr_assemble(n_rows, rows, cols, blocks, capacity=None):
+    """BlockMatrix from a list of 3x3 blocks on the device (int32 rows / cols
+    of shape [m], float64 blocks of shape [m, 3, 3] or [m, 9]): equal
+    (row, col) blocks summed in list order.  capacity: output blocks to
+    allocate (default m; a second call is made if the result needs more)."""
+    _need_cuda(rows, "rows", torch.int32)
+    _need_cuda(cols, "cols", torch.int32)
+    _need_cuda(blocks, "blocks", torch.float64)
+    m = rows.numel()
+    if cols.numel() != m or blocks.numel() != 9 * m:
+        raise ValueError("rows, cols and blocks must describe the same number of blocks")
+    L = _lib.load()
+    dev = rows.device
+    need = int(L.bcsr_assemble_workspace_size(int(n_rows), m))
+    ws = torch.empty(need + _ALIGN, dtype=torch.uint8, device=dev)
+    wsp = (ws.data_ptr() + _ALIGN - 1) // _ALIGN * _ALIGN
+    cap = m if capacity is None else int(capacity)
+    for _ in range(2):
+        row_ptr = torch.empty(int(n_rows) + 1, dtype=torch.int32, device=dev)
+        col_idx = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        val = torch.empty((max(cap, 1), 3, 3), dtype=torch.float64, device=dev)
+        nb = ctypes.c_int64(0)
+        rc = L.bcsr_assemble(int(n_rows), m, _ptr(rows), _ptr(cols), _ptr(blocks), _ptr(row_ptr), _ptr(col_idx),
+                             _ptr(val), cap, ctypes.byref(nb), ctypes.c_void_p(wsp), need, _stream())
+        if rc == MAS_INVALID_ARG and nb.value > cap:
+            cap = nb.value
+            continue
+        check("bcsr_assemble", rc)
+        return BlockMatrix(row_ptr, col_idx[: nb.value], val[: nb.value])
+    raise MasError("bcsr_assemble", MAS_INVALID_ARG)
 
 
 class MasPcg:
