@@ -23,7 +23,7 @@ struct Layout {
     size_t total = 0;
     size_t remap, map, perm_src, perm_full, rp0, ci0, lead1, anc, g_u1, srp, sci, srow, tptr, tidx;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
-    size_t ganc[kMaxLv], gpos[kMaxLv], cp_ptr[kMaxLv];
+    size_t ganc[kMaxLv], gpos[kMaxLv], gmask[kMaxLv], cp_ptr[kMaxLv], lmask;
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
     size_t b, x, r, z, p0, p1, q, r1, y[kMaxLv], cpart, P_sigma, P_rr, P_bb, P_rho0, P_rho1, st, flag;
     size_t inverse_bytes = 0;
@@ -141,6 +141,7 @@ void make_layout(mas_handle* h) {
     Y.rp0 = Y.take(I * (P.NS + 1));
     Y.ci0 = Y.take(I * P.nnzb);
     Y.lead1 = Y.take(I * P.NS);
+    Y.lmask = Y.take(sizeof(uint64_t) * P.NS);
     Y.anc = Y.take(I * P.anc.size());
     Y.g_u1 = Y.take(I * P.g_u1.size());
     if (P.sym) {
@@ -161,6 +162,7 @@ void make_layout(mas_handle* h) {
         if (l >= 2) {
             Y.ganc[l] = Y.take(I * P.ganc[l].size());
             Y.gpos[l] = Y.take(I * P.gpos[l].size());
+            Y.gmask[l] = Y.take(sizeof(uint64_t) * P.gmask[l].size());
             Y.cp_ptr[l] = Y.take(I * P.cp_ptr[l].size());
         }
     }
@@ -226,6 +228,7 @@ SolverView view(const mas_handle* h) {
         if (l >= 2) {
             v.ganc[l] = at<int>(h, Y.ganc[l]);
             v.gpos[l] = at<int>(h, Y.gpos[l]);
+            v.gmask[l] = at<uint64_t>(h, Y.gmask[l]);
             v.cp_ptr[l] = at<int>(h, Y.cp_ptr[l]);
         }
         if (l >= 1) v.y[l] = at<double>(h, Y.y[l]);
@@ -244,6 +247,7 @@ SolverView view(const mas_handle* h) {
     v.rp0 = at<int>(h, Y.rp0);
     v.ci0 = at<int>(h, Y.ci0);
     v.lead1 = at<int>(h, Y.lead1);
+    v.lmask = at<uint64_t>(h, Y.lmask);
     v.anc = at<int>(h, Y.anc);
     v.H64 = at<double>(h, Y.H64);
     v.H32 = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.H32) : nullptr;
@@ -308,6 +312,8 @@ int upload_plan(mas_handle* h, hipStream_t s) {
     HIP_TRY(put(Y.rp0, P.rp0));
     HIP_TRY(put(Y.ci0, P.ci0));
     HIP_TRY(put(Y.lead1, P.lead1));
+    HIP_TRY(hipMemcpyAsync(h->ws + Y.lmask, P.lmask.data(), sizeof(uint64_t) * P.lmask.size(), hipMemcpyHostToDevice,
+                           s));
     HIP_TRY(put(Y.anc, P.anc));
     HIP_TRY(put(Y.g_u1, P.g_u1));
     for (int l = 0; l < P.L; ++l) {
@@ -321,6 +327,8 @@ int upload_plan(mas_handle* h, hipStream_t s) {
         if (l >= 2) {
             HIP_TRY(put(Y.ganc[l], P.ganc[l]));
             HIP_TRY(put(Y.gpos[l], P.gpos[l]));
+            HIP_TRY(hipMemcpyAsync(h->ws + Y.gmask[l], P.gmask[l].data(), sizeof(uint64_t) * P.gmask[l].size(),
+                                   hipMemcpyHostToDevice, s));
             HIP_TRY(put(Y.cp_ptr[l], P.cp_ptr[l]));
         }
     }

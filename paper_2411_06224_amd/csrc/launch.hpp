@@ -58,6 +58,8 @@ struct SolverView {
     int W1;                       // restriction: most level-1 units in a group
     const int* ganc[kMaxLv];      // l >= 2: [G * W1] level-l unit of each level-1 unit of each group (-1 pad)
     const int* gpos[kMaxLv];      // l >= 2: [G * W1] its partial position, -1 if it writes none
+    const uint64_t* lmask;        // [NS] leader slots: lanes of the domain in the slot's level-1 unit
+    const uint64_t* gmask[kMaxLv];  // l >= 2: [G * W1] writers: group-local level-1 units below it
     const int* cp_ptr[kMaxLv];    // l >= 2: [S_l + 1]
     // stored slot-ordered matrix (9 planes: H64 of nsb, H32 of nnzb values)
     double* H64;

@@ -421,6 +421,17 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
             }
         }
     }
+    P.lmask.assign(P.NS, 0);
+    if (P.L > 1)
+        for (int d = 0; d < P.M; ++d)
+            for (int a = 0; a < N; ++a) {
+                const int u = P.lead1[d * N + a];
+                if (u < 0) continue;
+                uint64_t m = 0;
+                for (int b = 0; b < N; ++b)
+                    if (P.up[0][d * N + b] == u) m |= uint64_t(1) << b;
+                P.lmask[d * N + a] = m;
+            }
     P.anc.assign(static_cast<size_t>(std::max(P.L - 1, 0)) * P.NS, -1);
     for (int l = 1; l < P.L; ++l)
         for (int s = 0; s < P.NS; ++s) {
@@ -475,6 +486,7 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
     for (int g = 0; g < P.G; ++g) P.W1 = std::max(P.W1, P.g_u1[g + 1] - P.g_u1[g]);
     P.ganc.assign(P.L, {});
     P.gpos.assign(P.L, {});
+    P.gmask.assign(P.L, {});
     for (int l = 2; l < P.L; ++l) {
         P.ganc[l].assign(static_cast<size_t>(P.G) * P.W1, -1);
         P.gpos[l].assign(static_cast<size_t>(P.G) * P.W1, -1);
@@ -483,6 +495,18 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
                 const size_t o = static_cast<size_t>(g) * P.W1 + (t - P.g_u1[g]);
                 P.ganc[l][o] = P.anc1[l][t];
                 P.gpos[l][o] = P.lead_pos[l][t];
+            }
+        P.gmask[l].assign(static_cast<size_t>(P.G) * P.W1, 0);
+        if (P.W1 <= 64)
+            for (int g = 0; g < P.G; ++g) {
+                const int lo = P.g_u1[g], n1 = P.g_u1[g + 1] - lo;
+                for (int i = 0; i < n1; ++i) {
+                    if (P.lead_pos[l][lo + i] < 0) continue;
+                    uint64_t m = 0;
+                    for (int j = 0; j < n1; ++j)
+                        if (P.anc1[l][lo + j] == P.anc1[l][lo + i]) m |= uint64_t(1) << j;
+                    P.gmask[l][static_cast<size_t>(g) * P.W1 + i] = m;
+                }
             }
     }
 

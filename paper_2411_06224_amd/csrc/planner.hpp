@@ -67,6 +67,12 @@ struct Plan {
     // group; -1 past the group's own).
     int W1 = 1;
     std::vector<std::vector<int>> ganc, gpos;
+    // Member masks of the same sums: lmask[slot] (leader slots): the lanes of
+    // its domain in its level-1 unit; gmask[l][g * W1 + i] (writers): the
+    // group's level-1 units (local index) below the same level-l unit.
+    // Used when W1 <= 64.
+    std::vector<uint64_t> lmask;
+    std::vector<std::vector<uint64_t>> gmask;
     // Prolongation: unit of every slot at levels 1..L-1, [(l-1) * NS + slot], -1 = empty.
     std::vector<int> anc;
 

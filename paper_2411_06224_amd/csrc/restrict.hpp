@@ -11,25 +11,31 @@
 namespace maspcg {
 
 // Shared memory of the restriction, in doubles, for a group of RG slots with
-// at most W1 level-1 units and L levels: r1s[3 W1] doubles + up0[RG],
-// lead[RG], anc[(L-2) W1], pos[(L-2) W1] ints.
+// at most W1 level-1 units and L levels: r1s[3 W1] doubles, lmask[RG] and
+// gmask[(L-2) W1] 64-bit masks, then up0[RG], lead[RG], anc[(L-2) W1],
+// pos[(L-2) W1] ints.
 __host__ __device__ inline int restrict_smem_doubles(int RG, int W1, int L) {
-    const int ints = 2 * RG + 2 * (L > 2 ? L - 2 : 0) * W1;
-    return 3 * W1 + (ints + 1) / 2;
+    const int lv = L > 2 ? L - 2 : 0;
+    const int ints = 2 * RG + 2 * lv * W1;
+    return 3 * W1 + RG + lv * W1 + (ints + 1) / 2;
 }
 
 struct RestrictSmem {
     double* r1s;
+    uint64_t *lmask, *gmask;
     int *up0, *lead, *anc, *pos;
 };
 
 __device__ inline RestrictSmem restrict_layout(const SolverView& v, double* sm) {
+    const int lv = v.L > 2 ? v.L - 2 : 0;
     RestrictSmem r;
     r.r1s = sm;
-    r.up0 = reinterpret_cast<int*>(sm + 3 * v.W1);
+    r.lmask = reinterpret_cast<uint64_t*>(sm + 3 * v.W1);
+    r.gmask = r.lmask + v.RG;
+    r.up0 = reinterpret_cast<int*>(r.gmask + lv * v.W1);
     r.lead = r.up0 + v.RG;
     r.anc = r.lead + v.RG;
-    r.pos = r.anc + (v.L > 2 ? v.L - 2 : 0) * v.W1;
+    r.pos = r.anc + lv * v.W1;
     return r;
 }
 
@@ -53,6 +59,7 @@ __device__ inline GroupUnits restrict_prefetch(const SolverView& v, int g, doubl
         const bool in = slot < v.NS;
         S.up0[i] = in ? v.anc[slot] : -1;
         S.lead[i] = in ? v.lead1[slot] : -1;
+        S.lmask[i] = in ? v.lmask[slot] : 0;
     }
     if (v.L > 2) {
         const int tot = (v.L - 2) * W;
@@ -60,6 +67,7 @@ __device__ inline GroupUnits restrict_prefetch(const SolverView& v, int g, doubl
             const int l = 2 + o / W, i = o - (l - 2) * W;
             S.anc[o] = v.ganc[l][static_cast<long long>(g) * W + i];
             S.pos[o] = v.gpos[l][static_cast<long long>(g) * W + i];
+            S.gmask[o] = v.gmask[l][static_cast<long long>(g) * W + i];
         }
     }
     return GroupUnits{u1_lo, n1};
@@ -83,8 +91,13 @@ __device__ inline void restrict_group(const SolverView& v, GroupUnits gu, const 
         if (u < 0) continue;
         const int first = (ls / N) * N;
         double s = 0.0;
-        for (int a = 0; a < N; ++a)
-            if (S.up0[first + a] == u) s += rs[3 * (first + a) + c];
+        if (v.W1 <= 64) {
+            // the unit's lanes from the precomputed mask, ascending
+            for (uint64_t m = S.lmask[ls]; m; m &= m - 1) s += rs[3 * (first + __ffsll(static_cast<unsigned long long>(m)) - 1) + c];
+        } else {
+            for (int a = 0; a < N; ++a)
+                if (S.up0[first + a] == u) s += rs[3 * (first + a) + c];
+        }
         v.r1[3 * u + c] = s;
         S.r1s[3 * (u - u1_lo) + c] = s;
     }
@@ -96,11 +109,15 @@ __device__ inline void restrict_group(const SolverView& v, GroupUnits gu, const 
             const int l = li / n1, i = li - l * n1;
             const int pos = S.pos[l * v.W1 + i];
             if (pos < 0) continue;
-            const int* anc = S.anc + l * v.W1;
-            const int a = anc[i];
             double s = 0.0;
-            for (int j = 0; j < n1; ++j)
-                if (anc[j] == a) s += S.r1s[3 * j + c];
+            if (v.W1 <= 64) {
+                for (uint64_t m = S.gmask[l * v.W1 + i]; m; m &= m - 1) s += S.r1s[3 * (__ffsll(static_cast<unsigned long long>(m)) - 1) + c];
+            } else {
+                const int* anc = S.anc + l * v.W1;
+                const int a = anc[i];
+                for (int j = 0; j < n1; ++j)
+                    if (anc[j] == a) s += S.r1s[3 * j + c];
+            }
             v.cpart[3 * pos + c] = s;
         }
     }
