@@ -307,6 +307,23 @@ def main():
         log(f"Morton ordering: {ores['iterations']} its, {ms_morton:.3f} ms, {oinf['levels']} levels")
         osolver.close()
 
+        # supernode hierarchy rebuilt on the device from the analysed pattern
+        # (Sec. 4.1): the step repeated when contacts change the pattern
+        units_d, _ = solver.hierarchy_device(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            units_d, _ = solver.hierarchy_device(dev)
+        torch.cuda.synchronize()
+        ms_hier = 1e3 * (time.perf_counter() - t0) / args.steps
+        out["hierarchy_device"] = {
+            "ms": round(ms_hier, 4),
+            "levels": int(len(units_d)),
+            "matches_host_analysis": [int(u) for u in units_d] == list(info["units"]),
+            "host_symbolic_ms": round(t_symbolic * 1e3, 1),
+        }
+        log(f"device hierarchy: {ms_hier:.3f} ms, units {[int(u) for u in units_d]}")
+
         # forward + adjoint (loss 0.5 ||x - x*||^2, FP32 dL/dH) vs forward
         xt = torch.as_tensor(np.random.default_rng(4).standard_normal(3 * s.n), device=dev)
         for _ in range(max(args.warmup, 1)):

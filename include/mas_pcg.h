@@ -230,6 +230,28 @@ int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
                   int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/* Device bytes of scratch mas_hierarchy_device needs (after mas_analyze). */
+size_t mas_hierarchy_workspace_size(const mas_handle* h);
+
+/* The supernode hierarchy computed on the device (Supp. Alg. 2-5, with
+ * 64-lane masks: per level, adjacency masks of each domain's units from the
+ * slot-ordered pattern, connected components by a wave-level closure of the
+ * masks, supernodes numbered by their lowest lane through a ballot and a
+ * scan over domains), from the pattern and level-0 partition of the last
+ * mas_analyze.  It gives the same hierarchy as the host analysis, which
+ * still builds the solver's plans; the device construction is what the
+ * paper repeats each Newton step when contacts change the pattern.
+ *   levels, units: host, receive the level count and the units per level
+ *                  (units[MAS_MAX_LEVELS]), as mas_get_info;
+ *   sn: host, [levels * n_rows] unit of each node per level, as
+ *       mas_get_ordering; any output may be NULL.
+ *   workspace: device scratch, ws_bytes >= mas_hierarchy_workspace_size,
+ *              256-byte aligned.
+ * Synchronises the stream.  Errors: MAS_NOT_READY, MAS_INVALID_ARG,
+ * MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
+int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t* sn, void* workspace,
+                         size_t ws_bytes, void* stream);
+
 /* Host copy of the handle's static description (after mas_analyze). */
 int mas_get_info(const mas_handle* h, mas_info* out);
 

@@ -36,6 +36,8 @@ SYMBOLS = (
     "bcsr_assemble",
     "pcg_solve",
     "pcg_adjoint",
+    "mas_hierarchy_workspace_size",
+    "mas_hierarchy_device",
     "mas_get_info",
     "mas_get_ordering",
     "mas_get_timings",
@@ -142,6 +144,10 @@ def load():
     L.bcsr_assemble.argtypes = [i32, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_int64, P(ctypes.c_int64), vp,
                                 ctypes.c_size_t, vp]
     L.bcsr_assemble.restype = ctypes.c_int
+    L.mas_hierarchy_workspace_size.argtypes = [vp]
+    L.mas_hierarchy_workspace_size.restype = ctypes.c_size_t
+    L.mas_hierarchy_device.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.mas_hierarchy_device.restype = ctypes.c_int
     L.pcg_solve.argtypes = [vp, P(MasBcsr), vp, vp, P(PcgOptions), P(PcgResult), vp]
     L.pcg_solve.restype = ctypes.c_int
     L.pcg_adjoint.argtypes = [vp, P(MasBcsr), vp, vp, vp, vp, i32, P(PcgOptions), P(PcgResult), vp]

@@ -667,6 +667,70 @@ int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
     return MAS_OK;
 }
 
+namespace {
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t mas_hierarchy_workspace_size(const mas_handle* h) {
+    if (!h || !h->analyzed) return 0;
+    const Plan& P = h->plan;
+    size_t t = 0;
+    hierarchy_layout(nullptr, P.NS, kMaxLv, &t);
+    return t + round256(sizeof(int) * (P.NS + 1)) + round256(sizeof(int) * P.nnzb) + round256(sizeof(int) * P.NS);
+}
+
+int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t* sn, void* workspace,
+                         size_t ws_bytes, void* stream) {
+    if (!h) return MAS_INVALID_ARG;
+    if (!h->analyzed) return MAS_NOT_READY;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < mas_hierarchy_workspace_size(h)) return MAS_WORKSPACE_TOO_SMALL;
+    const Plan& P = h->plan;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(workspace);
+    size_t off = 0;
+    const HierLayout H = hierarchy_layout(ws, P.NS, kMaxLv, &off);
+    int* rp = reinterpret_cast<int*>(ws + off);
+    off += round256(sizeof(int) * (P.NS + 1));
+    int* ci = reinterpret_cast<int*>(ws + off);
+    off += round256(sizeof(int) * P.nnzb);
+    int* remap = reinterpret_cast<int*>(ws + off);
+    HIP_TRY(hipMemcpyAsync(rp, P.rp0.data(), sizeof(int) * (P.NS + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ci, P.ci0.data(), sizeof(int) * P.nnzb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(remap, P.remap.data(), sizeof(int) * P.NS, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_hier_init(H, P.NS, remap, s));
+    std::vector<int> u(1, P.NS), nd(1, P.M);
+    int occupied = P.V;
+    const int max_levels = h->opts.max_levels;
+    for (int l = 0;; ++l) {
+        if (nd[l] == 1) break;
+        if (max_levels > 0 && l + 1 >= max_levels) break;
+        if (l + 1 >= kMaxLv) break;
+        HIP_TRY(launch_hier_level(H, l, P.NS, P.N, u[l], rp, ci, remap, s));
+        int S = 0;
+        HIP_TRY(hipMemcpyAsync(&S, H.off + nd[l], sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (S == occupied) break;  // nothing merged
+        u.push_back(S);
+        nd.push_back((S + P.N - 1) / P.N);
+        occupied = S;
+    }
+    const int L = static_cast<int>(u.size());
+    if (levels) *levels = L;
+    if (units)
+        for (int l = 0; l < L; ++l) units[l] = u[l];
+    if (sn) {
+        std::vector<int> slot_sn(static_cast<size_t>(L) * P.NS);
+        HIP_TRY(hipMemcpyAsync(slot_sn.data(), H.sn, sizeof(int) * slot_sn.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int l = 0; l < L; ++l)
+            for (int i = 0; i < P.V; ++i) sn[static_cast<size_t>(l) * P.V + i] = slot_sn[static_cast<size_t>(l) * P.NS + P.map[i]];
+    }
+    return MAS_OK;
+}
+
 int mas_get_info(const mas_handle* h, mas_info* out) {
     if (!h || !out) return MAS_INVALID_ARG;
     if (!h->analyzed) return MAS_NOT_READY;

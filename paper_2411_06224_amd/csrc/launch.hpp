@@ -155,4 +155,16 @@ hipError_t launch_assemble_count(const AsmLayout& L, int n_rows, long long n_in,
 hipError_t launch_assemble_reduce(const AsmLayout& L, int n_rows, const double* blocks, int* row_ptr, int* col_idx,
                                   double* val, hipStream_t s);
 
+// hierarchy.hip: supernode hierarchy on the device.
+struct HierLayout {
+    unsigned long long* mask;
+    int *sn, *rep, *up, *cnt, *off, *totals;
+};
+HierLayout hierarchy_layout(char* ws, int NS, int L_max, size_t* total);
+hipError_t launch_hier_init(const HierLayout& H, int NS, const int* remap, hipStream_t s);
+// Level l -> l + 1 of the hierarchy: H.off[ceil(n_units / N)] receives the
+// number of next-level units, H.sn + (l + 1) NS the next unit of every slot.
+hipError_t launch_hier_level(const HierLayout& H, int l, int NS, int N, int n_units, const int* rp, const int* ci,
+                             const int* remap, hipStream_t s);
+
 }  // namespace maspcg

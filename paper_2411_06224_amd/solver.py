@@ -225,6 +225,32 @@ class MasPcg:
         )
         return mp, rm, sn
 
+    def hierarchy_device(self, device=None):
+        """Supernode hierarchy rebuilt on the device from the analysed pattern.
+
+        Returns ``(units[levels], sn[levels, V])`` in the layout of
+        :meth:`info` / :meth:`ordering`; the construction runs in the library's
+        kernels on torch's current stream (its scratch is a device tensor).
+        """
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        need = int(self._L.mas_hierarchy_workspace_size(self._h))
+        if need == 0:
+            raise MasError("mas_hierarchy_workspace_size", MAS_INVALID_ARG)
+        ws = torch.empty(need + _ALIGN, dtype=torch.uint8, device=dev)
+        base = (ws.data_ptr() + _ALIGN - 1) // _ALIGN * _ALIGN
+        levels = ctypes.c_int32(0)
+        units = np.zeros(_lib.MAS_MAX_LEVELS, np.int32)
+        sn = np.empty((_lib.MAS_MAX_LEVELS, self.n_rows), np.int32)
+        check(
+            "mas_hierarchy_device",
+            self._L.mas_hierarchy_device(
+                self._h, ctypes.byref(levels), units.ctypes.data_as(ctypes.c_void_p),
+                sn.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(base), ctypes.c_size_t(need), _stream()
+            ),
+        )
+        L = levels.value
+        return units[:L].copy(), sn[:L].copy()
+
     def timings(self):
         """Device ms of [coarse sums, inversion, H permute, PCG iterations] of the last calls."""
         out = (ctypes.c_double * 4)()
