@@ -370,6 +370,12 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
     // ---- hierarchy
     P.units.push_back(P.NS);
     P.ndom.push_back(P.M);
+    // room for every level up front: the loop holds references into rpA /
+    // ciA while it appends the next level
+    P.rpA.reserve(kMaxLevels);
+    P.ciA.reserve(kMaxLevels);
+    P.red_ptr.reserve(kMaxLevels);
+    P.red_src.reserve(kMaxLevels);
     P.rpA.emplace_back();  // level 0 uses rp0 / ci0
     P.ciA.emplace_back();
     P.red_ptr.emplace_back();
