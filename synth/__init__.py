@@ -18,8 +18,10 @@ from .workloads import (
     config_tiny,
     config_small,
     config_large,
+    config_membrane,
     WORKLOADS,
 )
+from .membrane import membrane_system
 
 __all__ = [
     "tet_cube",
@@ -34,5 +36,7 @@ __all__ = [
     "config_tiny",
     "config_small",
     "config_large",
+    "config_membrane",
+    "membrane_system",
     "WORKLOADS",
 ]

@@ -13,12 +13,16 @@ Each workload is a pure function of its parameters and seed:
 * ``config_large``  -- the 48^3 cube (117,649 nodes, 552,960 tets,
   352,947 DOF), nu = 0.49, E in {1e4, 1e6, 1e8} Pa, 20,000 contact pairs.
 * ``config_tiny``   -- 1^3 .. 4^3 cubes for brute-force checks.
+* ``config_membrane`` -- a 512 x 512-cell triangle sheet (263,169 nodes)
+  with strain-limiting and bending Hessians, coupled to 2,000 affine bodies
+  (8,000 block rows) by random 15x15 blocks (``synth.membrane``).
 """
 
 import numpy as np
 
 from .bcsr import BlockSystem, assemble_bcsr, graph_from_edges, random_psd_block
 from .fem import lumped_mass, snh_element_hessians
+from .membrane import membrane_system
 from .mesh import cube_surface_nodes, mesh_edges, tet_cube
 
 
@@ -146,7 +150,15 @@ def config_large(E=1e6, seed=1001, n_contacts=20000, keep_blocks=False):
     return cube_system(48, E, 0.49, n_contacts=n_contacts, seed=seed, keep_blocks=keep_blocks)
 
 
+def config_membrane(cells=512, n_bodies=2000, seed=1003):
+    """Stiff membrane plus affine bodies: 512^2 cells (263,169 nodes,
+    524,288 triangles, 785,408 bending pairs), 2,000 bodies of 4 block rows,
+    16 coupled sheet nodes each: 271,169 block rows."""
+    return membrane_system(cells, n_bodies, seed=seed)
+
+
 WORKLOADS = {
     "cube8": config_small,
     "cube48": config_large,
+    "membrane512": config_membrane,
 }
