@@ -20,6 +20,47 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kChunk = 1024;       // blocks staged in LDS per pass
 constexpr int kUserRows = 128;     // rows per workgroup for caller matrices
+// LDS planes of products are kPad doubles longer than a chunk, so that the
+// three components of one row, read by neighbouring lanes at the same
+// offset of consecutive planes, fall in different banks
+constexpr int kPad = 1;
+constexpr int kPlane = kChunk + kPad;
+
+// acc + p[lo] + p[lo + 1] + ... + p[hi - 1], added in this order; four
+// entries are loaded at a time so that their LDS latencies overlap
+__device__ __forceinline__ double sum_run(double acc, const double* p, int lo, int hi) {
+    int k = lo;
+    for (; k + 4 <= hi; k += 4) {
+        const double a0 = p[k], a1 = p[k + 1], a2 = p[k + 2], a3 = p[k + 3];
+        acc = (((acc + a0) + a1) + a2) + a3;
+    }
+    for (; k < hi; ++k) acc += p[k];
+    return acc;
+}
+
+// acc plus p[tl[tp] - cs], p[tl[tp + 1] - cs], ... in list order for the
+// entries of tl[tp, te) below ce (the lists ascend); tp advances past them.
+__device__ __forceinline__ double sum_listed(double acc, const double* p, const int* tl, int& tp, int te, int cs,
+                                             int ce) {
+    while (tp < te) {
+        int kk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) kk[j] = tp + j < te ? tl[tp + j] : ce;
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = kk[j] < ce ? p[kk[j] - cs] : 0.0;
+        int n = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (kk[j] < ce) {
+                acc += v[j];
+                ++n;
+            }
+        tp += n;
+        if (n < 4) break;
+    }
+    return acc;
+}
 
 // Block values: caller layout (9 consecutive values per block) or the
 // solver's planar layout (value c of block k at c * stride + k).
@@ -46,7 +87,7 @@ struct XDir {
 };
 
 // Row sums of rows [r0, r1) of H x.  Owner o = 3 (row - r0) + c is thread
-// o (acc[0]) or o - 256 (acc[1]); 3 (r1 - r0) <= 512.  prod: 3 * kChunk LDS.
+// o (acc[0]) or o - 256 (acc[1]); 3 (r1 - r0) <= 512.  prod: 3 * kPlane LDS.
 template <typename T, bool kPlanar, typename X>
 __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const int* __restrict__ ci,
                                             Blocks<T, kPlanar> H, X x, int r0, int r1, double* prod,
@@ -74,8 +115,8 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
             const double x0 = x.at(3 * j), x1 = x.at(3 * j + 1), x2 = x.at(3 * j + 2);
             const int e = k - cs;
             prod[e] = H.at(k, 0) * x0 + H.at(k, 1) * x1 + H.at(k, 2) * x2;
-            prod[kChunk + e] = H.at(k, 3) * x0 + H.at(k, 4) * x1 + H.at(k, 5) * x2;
-            prod[2 * kChunk + e] = H.at(k, 6) * x0 + H.at(k, 7) * x1 + H.at(k, 8) * x2;
+            prod[kPlane + e] = H.at(k, 3) * x0 + H.at(k, 4) * x1 + H.at(k, 5) * x2;
+            prod[2 * kPlane + e] = H.at(k, 6) * x0 + H.at(k, 7) * x1 + H.at(k, 8) * x2;
         }
         __syncthreads();
 #pragma unroll
@@ -84,7 +125,7 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
             if (o < nown) {
                 const int c = o % 3;
                 const int lo = max(rb[q], cs), hi = min(re[q], ce);
-                for (int k = lo; k < hi; ++k) acc[q] += prod[c * kChunk + (k - cs)];
+                acc[q] = sum_run(acc[q], prod + c * kPlane, lo - cs, hi - cs);
             }
         }
         __syncthreads();
@@ -102,6 +143,7 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
 // in stored order.  xs: x on the group's own slots (LDS); external columns
 // are gathered through X; tl: the group's transposed entries (LDS).
 constexpr int kSymChunk = 512;
+constexpr int kSymPlane = kSymChunk + kPad;
 
 template <typename T, typename X>
 __device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restrict__ H, X xg, const double* xs,
@@ -149,13 +191,13 @@ __device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restr
                          h8 = static_cast<double>(H[8 * st + k]);
             const int e = k - cs;
             prod[e] = h0 * x0 + h1 * x1 + h2 * x2;
-            prod[kSymChunk + e] = h3 * x0 + h4 * x1 + h5 * x2;
-            prod[2 * kSymChunk + e] = h6 * x0 + h7 * x1 + h8 * x2;
+            prod[kSymPlane + e] = h3 * x0 + h4 * x1 + h5 * x2;
+            prod[2 * kSymPlane + e] = h6 * x0 + h7 * x1 + h8 * x2;
             if (internal && jl != r) {
                 const double y0 = xs[3 * r], y1 = xs[3 * r + 1], y2 = xs[3 * r + 2];
-                prod[3 * kSymChunk + e] = h0 * y0 + h3 * y1 + h6 * y2;
-                prod[4 * kSymChunk + e] = h1 * y0 + h4 * y1 + h7 * y2;
-                prod[5 * kSymChunk + e] = h2 * y0 + h5 * y1 + h8 * y2;
+                prod[3 * kSymPlane + e] = h0 * y0 + h3 * y1 + h6 * y2;
+                prod[4 * kSymPlane + e] = h1 * y0 + h4 * y1 + h7 * y2;
+                prod[5 * kSymPlane + e] = h2 * y0 + h5 * y1 + h8 * y2;
             }
         }
         __syncthreads();
@@ -165,13 +207,8 @@ __device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restr
             if (o < nown) {
                 const int c = o % 3;
                 const int lo = max(rb[q], cs), hi = min(re[q], ce);
-                for (int k = lo; k < hi; ++k) acc[q] += prod[c * kSymChunk + (k - cs)];
-                while (tp[q] < te[q]) {
-                    const int kk = tl[tp[q]];
-                    if (kk >= ce) break;
-                    acc[q] += prod[(3 + c) * kSymChunk + (kk - cs)];
-                    ++tp[q];
-                }
+                acc[q] = sum_run(acc[q], prod + c * kSymPlane, lo - cs, hi - cs);
+                acc[q] = sum_listed(acc[q], prod + (3 + c) * kSymPlane, tl, tp[q], te[q], cs, ce);
             }
         }
         __syncthreads();
@@ -182,7 +219,7 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* __restrict__ rp,
                                                          const int* __restrict__ ci, const T* __restrict__ val,
                                                          const double* __restrict__ x, double* __restrict__ y) {
-    __shared__ double prod[3 * kChunk];
+    __shared__ double prod[3 * kPlane];
     const int r0 = blockIdx.x * kUserRows;
     const int r1 = min(r0 + kUserRows, n_rows);
     double acc[2];
@@ -202,7 +239,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* _
 // direction entry has the same bits in every workgroup that reads it.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __restrict__ H, int k) {
-    __shared__ double prod[3 * kChunk];
+    __shared__ double prod[3 * kPlane];
     __shared__ double buf[256];
     if (v.st->done) return;
     const int g = xcd_group(blockIdx.x, v.G);
@@ -243,7 +280,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
 // columns outside the group.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T* __restrict__ H, int k) {
-    __shared__ double prod[6 * kSymChunk];
+    __shared__ double prod[6 * kSymPlane];
     __shared__ double buf[256];
     extern __shared__ double dyn[];  // xs[3 RG] doubles + tl[maxT] ints
     if (v.st->done) return;
@@ -305,7 +342,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
 // restriction of the new residual to the coarse levels.
 template <int kMode, bool kSym>
 __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __restrict__ out) {
-    __shared__ double prod[(kSym ? 6 * kSymChunk : 3 * kChunk)];
+    __shared__ double prod[(kSym ? 6 * kSymPlane : 3 * kPlane)];
     __shared__ double scratch[kThreads / 64];
     extern __shared__ double dyn[];  // rs[3*RG] + restriction scratch (+ xs[3*RG] + tl[maxT] ints)
     if (kMode == kResidReplace && v.st->done) return;
