@@ -88,10 +88,12 @@ struct XDir {
 
 // Row sums of rows [r0, r1) of H x.  Owner o = 3 (row - r0) + c is thread
 // o (acc[0]) or o - 256 (acc[1]); 3 (r1 - r0) <= 512.  prod: 3 * kPlane LDS.
-template <typename T, bool kPlanar, typename X>
+// kLds: x of the columns r0 .. r1 - 1 is read from xs (LDS), the others
+// through X.
+template <typename T, bool kPlanar, typename X, bool kLds = false>
 __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const int* __restrict__ ci,
                                             Blocks<T, kPlanar> H, X x, int r0, int r1, double* prod,
-                                            double (&acc)[2]) {
+                                            double (&acc)[2], const double* xs = nullptr) {
     const int t = threadIdx.x;
     const int nown = 3 * (r1 - r0);
     int rb[2], re[2];
@@ -112,7 +114,17 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
 #pragma unroll 8
         for (int k = cs + t; k < ce; k += kThreads) {
             const int j = ci[k];
-            const double x0 = x.at(3 * j), x1 = x.at(3 * j + 1), x2 = x.at(3 * j + 2);
+            double x0, x1, x2;
+            const int jl = j - r0;
+            if (kLds && jl >= 0 && jl < r1 - r0) {
+                x0 = xs[3 * jl];
+                x1 = xs[3 * jl + 1];
+                x2 = xs[3 * jl + 2];
+            } else {
+                x0 = x.at(3 * j);
+                x1 = x.at(3 * j + 1);
+                x2 = x.at(3 * j + 2);
+            }
             const int e = k - cs;
             prod[e] = H.at(k, 0) * x0 + H.at(k, 1) * x1 + H.at(k, 2) * x2;
             prod[kPlane + e] = H.at(k, 3) * x0 + H.at(k, 4) * x1 + H.at(k, 5) * x2;
@@ -233,46 +245,65 @@ __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* _
 
 // PCG iteration k over the solver's group of slots: the new direction
 // p_k = z_{k-1} + beta_{k-1} p_{k-1} (beta = rho_{k-1} / rho_{k-2} summed from
-// the group partials; p_1 = z_0) is formed on the fly wherever H gathers it
-// and stored for the group's own rows; q = H p_k and the partial of p_k^T q.
-// Every workgroup forms the same beta and the same fused multiply-add, so a
-// direction entry has the same bits in every workgroup that reads it.
+// the group partials; p_1 = z_0) is formed first on the group's own slots
+// (into LDS and p_k) and, for columns outside the group, wherever H gathers
+// it; q = H p_k and the partial of p_k^T q.  Every workgroup forms the same
+// beta and the same fused multiply-add, so a direction entry has the same
+// bits in every workgroup that reads it.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __restrict__ H, int k) {
     __shared__ double prod[3 * kPlane];
     __shared__ double buf[256];
+    __shared__ double xs[384];
     if (v.st->done) return;
+    const int t = threadIdx.x;
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
-    // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded
-    // it (loaded before the partial sum's barriers)
+    const int nown = 3 * (r1 - r0);
+    // every independent load before the first barrier
+    const double* pold = k > 1 ? v.p[(k - 1) & 1] : v.z;  // k = 1: p_1 = z_0 (+ 0 * z_0)
+    double zo[2], po[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        zo[q] = po[q] = 0.0;
+        if (o < nown) {
+            zo[q] = v.z[3LL * r0 + o];
+            po[q] = pold[3LL * r0 + o];
+        }
+    }
+    // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
     const double rk2 = v.st->rho[k & 1];
     const double rk1 = sum_partials(v.P_rho[(k - 1) & 1], v.G, buf);
-    if (g == 0 && threadIdx.x == 0) v.st->rho[(k - 1) & 1] = rk1;
-    double beta = 0.0;
-    const double* pold = v.z;  // k = 1: p_1 = z_0 (+ 0 * z_0)
-    if (k > 1) {
-        beta = rk1 / rk2;
-        pold = v.p[(k - 1) & 1];
-    }
-    const XDir dir{v.z, pold, beta};
-    double acc[2];
-    stream_rows<T, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, dir, r0, r1, prod, acc);
+    if (g == 0 && t == 0) v.st->rho[(k - 1) & 1] = rk1;
+    const double beta = k > 1 ? rk1 / rk2 : 0.0;
     double* pk = v.p[k & 1];
+    double pv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        pv[q] = 0.0;
+        if (o < nown) {
+            pv[q] = __fma_rn(beta, po[q], zo[q]);
+            pk[3LL * r0 + o] = pv[q];
+            xs[o] = pv[q];
+        }
+    }
+    __syncthreads();
+    double acc[2];
+    stream_rows<T, true, XDir, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, XDir{v.z, pold, beta}, r0, r1, prod,
+                                     acc, xs);
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int o = threadIdx.x + q * kThreads;
-        if (o < 3 * (r1 - r0)) {
-            const long long i = 3LL * r0 + o;
-            const double pv = dir.at(i);
-            pk[i] = pv;
-            v.q[i] = acc[q];
-            part += pv * acc[q];
+        const int o = t + q * kThreads;
+        if (o < nown) {
+            v.q[3LL * r0 + o] = acc[q];
+            part += pv[q] * acc[q];
         }
     }
     part = block_sum(part, buf);
-    if (threadIdx.x == 0) v.P_sigma[g] = part;
+    if (t == 0) v.P_sigma[g] = part;
 }
 
 // k_spmv_pq on the group-symmetric storage: the group forms the new
