@@ -237,6 +237,36 @@ def main():
         out["kernels"] = per
         log("kernels:", json.dumps(per))
 
+        # achievable HBM bandwidth for context: a triad a = b + s c over three
+        # 1 GiB arrays (far beyond the 256 MB last-level cache), torch's own
+        # elementwise kernel, timed with events on the current stream
+        nt = (1 << 30) // 8
+        ta, tb, tc = (torch.empty(nt, dtype=torch.float64, device=dev) for _ in range(3))
+        tb.fill_(1.0)
+        tc.fill_(2.0)
+        torch.add(tb, tc, alpha=0.5, out=ta)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            torch.add(tb, tc, alpha=0.5, out=ta)
+        e1.record()
+        torch.cuda.synchronize()
+        triad = 3 * nt * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del ta, tb, tc
+        out["roofline"]["achievable_triad_GBs"] = round(triad, 1)
+        out["roofline"]["frac_of_triad"] = round(ach / triad, 4)
+        log(f"triad: {triad:.0f} GB/s")
+
+        # batched domain inversion: about (3N)^3 flops per domain (FP64, MFMA)
+        n3 = (3 * info["domain_size"]) ** 3
+        inv_flop = sum(info["domains"][l] for l in range(info["levels"])) * n3
+        out["inversion"] = {
+            "ms": round(ph[1], 4),
+            "gflop": round(inv_flop / 1e9, 3),
+            "TFLOPs": round(inv_flop / (ph[1] * 1e-3) / 1e12, 2) if ph[1] > 0 else None,
+            "frac_of_fp64_mfma_peak": round(inv_flop / (ph[1] * 1e-3) / 78.6e12, 4) if ph[1] > 0 else None,
+        }
+
         # mixed precision on the same system
         msolver = mp.MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=args.domain_size, precision="mixed")
         for _ in range(max(args.warmup, 1)):

@@ -217,3 +217,23 @@ def test_given_partition_rejects_invalid():
     neg = ok.copy()
     neg[0] = -1
     assert rc(neg, int(ok.max()) + 1) == _lib.MAS_INVALID_ARG
+
+
+def test_hierarchy_device_argument_checks():
+    """mas_hierarchy_device validates its arguments on the host before any
+    device work: not analysed, missing or misaligned workspace, too small."""
+    L = _lib.load()
+    h = ctypes.c_void_p()
+    assert L.mas_create(None, ctypes.byref(h)) == _lib.MAS_OK
+    assert L.mas_hierarchy_workspace_size(h) == 0
+    assert L.mas_hierarchy_device(h, None, None, None, ctypes.c_void_p(256), 1 << 20, None) == _lib.MAS_NOT_READY
+    L.mas_destroy(h)
+    s = small_cube()
+    S = MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16)
+    need = S._L.mas_hierarchy_workspace_size(S._h)
+    assert need > 0
+    call = lambda ws, n: S._L.mas_hierarchy_device(S._h, None, None, None, ws, n, None)
+    assert call(None, need) == _lib.MAS_INVALID_ARG
+    assert call(ctypes.c_void_p(4096 + 8), need) == _lib.MAS_INVALID_ARG  # not 256-byte aligned
+    assert call(ctypes.c_void_p(4096), need - 1) == _lib.MAS_WORKSPACE_TOO_SMALL
+    assert S._L.mas_hierarchy_device(None, None, None, None, ctypes.c_void_p(4096), need, None) == _lib.MAS_INVALID_ARG
