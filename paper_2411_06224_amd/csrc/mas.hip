@@ -242,6 +242,7 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
 
 // ------------------------------------------------------------------ apply
 constexpr int kFlagX0 = 1, kFlagMixed = 2, kFlagRrTrue = 4;
+constexpr int kRound = 4;  // coarse partials loaded per round by one lane
 
 // Workgroup 0 of the coarse launch takes the convergence decision of the
 // iteration: it sums the ||r||^2 partials (and ||b||^2 for the first
@@ -335,8 +336,27 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
         const int a = t >> 4, sub = t & 15;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         if (a < nu) {
+            // the lane's partials m0 + sub, + 16, + 32, ... in this order;
+            // kRound are loaded per round so that their latencies overlap (a
+            // unit of the top levels has partials from about a hundred groups)
             const int m0 = cp[u0 + a], m1 = cp[u0 + a + 1];
-            for (int m = m0 + sub; m < m1; m += 16) {
+            int m = m0 + sub;
+            for (; m + 16 * (kRound - 1) < m1; m += 16 * kRound) {
+                double a0[kRound], a1[kRound], a2[kRound];
+#pragma unroll
+                for (int j = 0; j < kRound; ++j) {
+                    a0[j] = v.cpart[3 * (m + 16 * j)];
+                    a1[j] = v.cpart[3 * (m + 16 * j) + 1];
+                    a2[j] = v.cpart[3 * (m + 16 * j) + 2];
+                }
+#pragma unroll
+                for (int j = 0; j < kRound; ++j) {
+                    s0 += a0[j];
+                    s1 += a1[j];
+                    s2 += a2[j];
+                }
+            }
+            for (; m < m1; m += 16) {
                 s0 += v.cpart[3 * m];
                 s1 += v.cpart[3 * m + 1];
                 s2 += v.cpart[3 * m + 2];
