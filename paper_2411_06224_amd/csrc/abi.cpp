@@ -171,8 +171,9 @@ void make_layout(mas_handle* h) {
     for (int l = 1; l < P.L; ++l) Y.A[l] = Y.take(Dd * 9 * P.ciA[l].size());
     for (int l = 0; l < P.L; ++l) {
         const size_t cnt = static_cast<size_t>(P.ndom[l]) * n * n;
-        Y.inv64[l] = Y.take(Dd * cnt);
-        Y.inverse_bytes += (mixed ? F : Dd) * cnt;
+        const size_t cnt64 = (l == 0 && P.N == 16) ? static_cast<size_t>(P.ndom[l]) * kPacked : cnt;
+        Y.inv64[l] = Y.take(Dd * cnt64);
+        Y.inverse_bytes += mixed ? F * cnt : Dd * cnt64;
         if (mixed) Y.inv32[l] = Y.take(F * cnt);
     }
     // slot vectors padded to whole groups so group kernels never branch on the tail
@@ -202,6 +203,7 @@ SolverView view(const mas_handle* h) {
     SolverView v{};
     v.V = P.V;
     v.N = P.N;
+    v.packed0 = P.N == 16 ? 1 : 0;
     v.M = P.M;
     v.NS = P.NS;
     v.L = P.L;
@@ -270,6 +272,7 @@ BuildView build_view(const mas_handle* h) {
     BuildView b{};
     b.L = P.L;
     b.N = P.N;
+    b.packed0 = P.N == 16 ? 1 : 0;
     b.nnzb = P.nnzb;
     for (int l = 0; l < P.L; ++l) {
         b.units[l] = P.units[l];

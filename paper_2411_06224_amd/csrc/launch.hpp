@@ -34,6 +34,7 @@ void launch_kernel(F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t 
 struct SolverView {
     int V, N, M, NS, L, nnzb;
     int D0, RG, G;  // work groups: D0 level-0 domains = RG slots; G groups
+    int packed0;    // 1: FP64 level-0 inverses symmetric-packed (N == 16)
     int sym;        // 1: H64 holds the group-symmetric storage (nsb blocks), 0: the full slot-ordered H;
                     // H32 (mixed) always holds the full storage (nnzb blocks)
     int nsb;        // blocks of the stored slot-ordered H (H64 / H32 planes)
@@ -80,9 +81,19 @@ struct SolverView {
     int* flag;  // inversion status
 };
 
+// The FP64 level-0 inverses of domain size 16 are stored symmetric-packed:
+// the lower triangle of the 48 x 48 inverse column by column (column j holds
+// rows j..47, so entry (i, j), i >= j, sits at packed_col(j) + i - j), 1176
+// entries per domain.  The FP32 copy, other levels and other domain sizes
+// keep the full column-major (3N)^2 block.
+constexpr int kPackedN = 48;
+constexpr int kPacked = kPackedN * (kPackedN + 1) / 2;
+__host__ __device__ constexpr int packed_col(int j) { return j * kPackedN - (j * (j - 1)) / 2; }
+
 // Build-phase views.
 struct BuildView {
     int L, N, nnzb;
+    int packed0;  // FP64 level-0 inverses symmetric-packed (N == 16)
     int units[kMaxLv];
     int ndom[kMaxLv];
     int nnzA[kMaxLv];

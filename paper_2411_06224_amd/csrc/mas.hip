@@ -10,11 +10,12 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Inverse entries in the apply.  The level-0 FP64 inverses (136 MB at the
-// 48^3 cube) do not fit the 256 MB MALL next to H, so they are streamed with
-// non-temporal loads that leave the caches to H, the vectors and the coarse
-// inverses (kStream); the FP32 set of the mixed solve fits and is read
-// through the caches, as are the coarse levels (16 MB).
+// Inverse entries in the apply.  Full-layout level-0 FP64 inverses (136 MB
+// at the 48^3 cube) do not fit the 256 MB MALL next to H, so they are
+// streamed with non-temporal loads that leave the caches to H, the vectors
+// and the coarse inverses (kStream); the symmetric-packed FP64 set (69 MB),
+// the FP32 set of the mixed solve and the coarse levels (16 MB) fit and are
+// read through the caches.
 template <typename TI, bool kStream = true>
 __device__ __forceinline__ double inv_load(const TI* p) {
     if constexpr (sizeof(TI) == 8 && kStream)
@@ -227,17 +228,29 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
     }
     if (!ok && lane == 0) atomicOr(B.flag, 1);
 
+    const bool packed = l == 0 && B.packed0;
+    if (packed) {
+        // FP64: symmetric-packed lower triangle (the mean of the two
+        // triangles of the computed inverse), zero on empty lanes
+        double* o64 = B.inv64[0] + (long long)d * kPacked;
+        for (int j = 0; j < kPackedN; ++j)
+            for (int i = j + lane; i < kPackedN; i += 64) {
+                const bool live = ((occ >> (i / 3)) & 1ull) && ((occ >> (j / 3)) & 1ull);
+                o64[packed_col(j) + i - j] = live ? 0.5 * (A[i * LD + j] + A[j * LD + i]) : 0.0;
+            }
+    }
     // column-major n x n, zero rows/columns on empty lanes
     const long long off = (long long)d * n * n;
-    double* o64 = B.inv64[l] + off;
+    double* o64 = packed ? nullptr : B.inv64[l] + off;
     float* o32 = want32 ? B.inv32[l] + off : nullptr;
-    for (int e = lane; e < n * n; e += 64) {
-        const int col = e / n, row = e - col * n;
-        const bool live = ((occ >> (row / 3)) & 1ull) && ((occ >> (col / 3)) & 1ull);
-        const double val = live ? A[row * LD + col] : 0.0;
-        o64[e] = val;
-        if (o32) o32[e] = static_cast<float>(val);
-    }
+    if (o64 || o32)
+        for (int e = lane; e < n * n; e += 64) {
+            const int col = e / n, row = e - col * n;
+            const bool live = ((occ >> (row / 3)) & 1ull) && ((occ >> (col / 3)) & 1ull);
+            const double val = live ? A[row * LD + col] : 0.0;
+            if (o64) o64[e] = val;
+            if (o32) o32[e] = static_cast<float>(val);
+        }
 }
 
 // ------------------------------------------------------------------ apply
@@ -487,6 +500,107 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
     if (t == 0) v.P_rho[k & 1][g] = part;
 }
 
+// Level 0 with the symmetric-packed FP64 inverses (domain size 16), over a
+// group of D0 domains: the packed inverses of two domains at a time
+// (18.8 KB, contiguous) are staged in LDS with coalesced loads, the next
+// pair's loads in flight (in registers) while the current pair is
+// multiplied.  (With FP32 inverses the full layout streams faster: the
+// staging rounds, not the bytes, then bound the kernel.)  Four
+// threads per row each take twelve columns: entry (i, kk) of the inverse is
+// (kk, i) of the stored lower triangle when kk > i.  The rows' sums go to
+// LDS; then, one thread per DOF as in k_apply_level0,
+//   z = Inv_{0,d} r_d + sum_{l >= 1} y_l[unit of the slot at level l]
+// and the partial of rho = r^T z.  Returns at once after a stop.
+constexpr int kPairs = 2;                                // domains staged per round
+constexpr int kStageLoads = (kPairs * kPacked + 383) / 384;  // entries per thread and round
+
+template <typename TI, int kMode>
+__global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k) {
+    __shared__ double rs[384];
+    __shared__ double zs[384];
+    __shared__ TI stage[kPairs * kPacked];
+    __shared__ double red[8];
+    const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
+    if (kMode != kApplyPlain && v.st->done) return;
+    const int nd = min(v.D0, v.M - g * v.D0);  // domains of this group
+    const bool live = t < nd * 48;
+    const long long base = 3LL * g * v.RG;
+    const int slot = g * v.RG + t / 3, c = t % 3;
+    const TI* inv;
+    if constexpr (sizeof(TI) == 8)
+        inv = v.inv64[0];
+    else
+        inv = v.inv32[0];
+    inv += static_cast<long long>(g) * v.D0 * kPacked;
+    const int rounds = (nd + kPairs - 1) / kPairs;
+    // the first pair, then the corrections of the slot (prolongation) and r
+    TI nxt[kStageLoads];
+    auto fetch = [&](int p) {
+        const int cnt = min(kPairs, nd - kPairs * p) * kPacked;
+        const TI* src = inv + static_cast<long long>(kPairs * p) * kPacked;
+#pragma unroll
+        for (int j = 0; j < kStageLoads; ++j) {
+            const int e = t + 384 * j;
+            nxt[j] = e < cnt ? inv_load<TI, false>(src + e) : TI(0);
+        }
+    };
+    fetch(0);
+    int u[kPreLevels];
+#pragma unroll
+    for (int j = 0; j < kPreLevels; ++j)
+        u[j] = (live && j + 1 < v.L) ? v.anc[static_cast<long long>(j) * v.NS + slot] : -1;
+    const double rv = live ? v.r[base + t] : 0.0;
+    double ycor[kPreLevels];
+#pragma unroll
+    for (int j = 0; j < kPreLevels; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
+    if (t < 384) rs[t] = rv;
+    const int row = t >> 2, q = t & 3;  // 96 rows of a pair, four quarters each
+    const int dl = row / 48, i = row - 48 * dl;
+    for (int p = 0; p < rounds; ++p) {
+        const int cnt = min(kPairs, nd - kPairs * p) * kPacked;
+#pragma unroll
+        for (int j = 0; j < kStageLoads; ++j) {
+            const int e = t + 384 * j;
+            if (e < cnt) stage[e] = nxt[j];
+        }
+        __syncthreads();  // the pair (and, the first time, r) are visible
+        if (p + 1 < rounds) fetch(p + 1);
+        const int d = kPairs * p + dl;
+        double s = 0.0;
+        if (d < nd) {
+            const TI* Ad = stage + dl * kPacked;
+            const double* rd = rs + 48 * d;
+#pragma unroll
+            for (int m = 0; m < 12; ++m) {
+                const int kk = 12 * q + m;
+                const int idx = kk <= i ? packed_col(kk) + i - kk : packed_col(i) + kk - i;
+                s += static_cast<double>(Ad[idx]) * rd[kk];
+            }
+        }
+        // the row's four quarters, added as (q0 + q1) + (q2 + q3)
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (q == 0 && d < nd) zs[48 * d + i] = s;
+        __syncthreads();  // stage free for the next pair
+    }
+    double zv = 0.0;
+    if (live) {
+        double acc = zs[t];
+#pragma unroll
+        for (int j = 0; j < kPreLevels; ++j)
+            if (u[j] >= 0) acc += ycor[j];
+        for (int l = kPreLevels + 1; l < v.L; ++l) {
+            const int uu = v.anc[static_cast<long long>(l - 1) * v.NS + slot];
+            if (uu >= 0) acc += v.y[l][3 * uu + c];
+        }
+        zv = acc;
+        v.z[base + t] = zv;
+    }
+    if (kMode == kApplyPlain) return;
+    const double part = block_sum(rv * zv, red);
+    if (t == 0) v.P_rho[k & 1][g] = part;
+}
+
 DomTable make_table(const int* ndom, int first, int L) {
     DomTable t{};
     int acc = 0;
@@ -558,6 +672,15 @@ hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, int k, d
 template <typename TI, int kN>
 void launch_level0_t(const SolverView& v, int mode, int k, hipStream_t s) {
     dim3 g(v.G), b(round_waves(3 * v.RG));
+    if (kN == 16 && v.packed0 && sizeof(TI) == 8) {
+        if (mode == kApplyPlain)
+            launch_kernel((k_apply_level0_packed<TI, kApplyPlain>), g, b, 0, s, v, k);
+        else if (mode == kApplyInit)
+            launch_kernel((k_apply_level0_packed<TI, kApplyInit>), g, b, 0, s, v, k);
+        else
+            launch_kernel((k_apply_level0_packed<TI, kApplyIter>), g, b, 0, s, v, k);
+        return;
+    }
     if (mode == kApplyPlain)
         launch_kernel((k_apply_level0<TI, kN, kApplyPlain>), g, b, 0, s, v, k);
     else if (mode == kApplyInit)
