@@ -72,6 +72,8 @@ def algorithmic_bytes(info, mixed):
     val = 36 if mixed else 72
     inv = 4 if mixed else 8
     coarse_y = sum(8 * 3 * info["domains"][l] * N for l in range(1, L))
+    # level-0 inverses: FP64 symmetric-packed for N = 16 (n (n + 1) / 2 entries), else full
+    inv0 = info["domains"][0] * (n * (n + 1) // 2 if (N == 16 and not mixed) else n * n) * inv
     out = {
         # stored blocks (each block pair inside a work group once): values,
         # column index and local row; row pointers and transposed-entry lists;
@@ -79,7 +81,7 @@ def algorithmic_bytes(info, mixed):
         # fused in), new direction and q written
         "spmv": nsb * (val + 4 + 1) + 8 * (NS + 1) + 4 * (nnzb - nsb) + 4 * vb,
         # level-0 inverses, r read, z written, per-slot coarse ids, coarse corrections
-        "apply_level0": info["domains"][0] * n * n * inv + 2 * vb + 4 * (L - 1) * NS + coarse_y,
+        "apply_level0": inv0 + 2 * vb + 4 * (L - 1) * NS + coarse_y,
         # coarse inverses, restricted residual read, y written
         "apply_coarse": sum(info["domains"][l] * n * n * inv for l in range(1, L))
         + (8 * 3 * info["units"][1] if L > 1 else 0)
