@@ -545,14 +545,7 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
         }
     };
     fetch(0);
-    int u[kPreLevels];
-#pragma unroll
-    for (int j = 0; j < kPreLevels; ++j)
-        u[j] = (live && j + 1 < v.L) ? v.anc[static_cast<long long>(j) * v.NS + slot] : -1;
     const double rv = live ? v.r[base + t] : 0.0;
-    double ycor[kPreLevels];
-#pragma unroll
-    for (int j = 0; j < kPreLevels; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
     if (t < 384) rs[t] = rv;
     const int row = t >> 2, q = t & 3;  // 96 rows of a pair, four quarters each
     const int dl = row / 48, i = row - 48 * dl;
@@ -583,6 +576,15 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
         if (q == 0 && d < nd) zs[48 * d + i] = s;
         __syncthreads();  // stage free for the next pair
     }
+    // the corrections of the slot (prolongation), loaded after the rounds:
+    // registers held through them would cost a workgroup per CU
+    int u[kPreLevels];
+#pragma unroll
+    for (int j = 0; j < kPreLevels; ++j)
+        u[j] = (live && j + 1 < v.L) ? v.anc[static_cast<long long>(j) * v.NS + slot] : -1;
+    double ycor[kPreLevels];
+#pragma unroll
+    for (int j = 0; j < kPreLevels; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
     double zv = 0.0;
     if (live) {
         double acc = zs[t];
