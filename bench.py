@@ -238,6 +238,16 @@ def main():
         }
         out["kernels"] = per
         log("kernels:", json.dumps(per))
+        # the paper's breakdown of a solve (Table 1 columns): preconditioner
+        # construction (coarse sums + inversion), preconditioner application
+        # (MAS apply kernels) and the rest of the CG iteration (SpMV, x/r
+        # update), from the instrumented solve's per-kernel totals
+        tot = {k: kt[k][0] for k in kt}
+        out["paper_breakdown_ms"] = {
+            "PPC": round(ph[0] + ph[1], 4),
+            "PPR": round(tot.get("apply_coarse", 0.0) + tot.get("apply_level0", 0.0), 4),
+            "CGR": round(tot.get("spmv", 0.0) + tot.get("update", 0.0) + tot.get("residual", 0.0), 4),
+        }
 
         # achievable HBM bandwidth for context: a triad a = b + s c over three
         # 1 GiB arrays (far beyond the 256 MB last-level cache), torch's own
@@ -338,6 +348,26 @@ def main():
         }
         log(f"Morton ordering: {ores['iterations']} its, {ms_morton:.3f} ms, {oinf['levels']} levels")
         osolver.close()
+
+        # hierarchy depth ablation: the additive sum over levels (Supp. Eq. 6)
+        # with the level cap at 1 (block Jacobi over the level-0 domains) and
+        # 2, against the full hierarchy of the headline solve
+        depth = {}
+        for ml in (1, 2):
+            dsolver = mp.MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=args.domain_size,
+                                max_levels=ml)
+            step(dsolver, args.tol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, dres = step(dsolver, args.tol)
+            torch.cuda.synchronize()
+            depth[f"max_levels_{ml}"] = {"iterations": dres["iterations"],
+                                         "ms_per_solve": round(1e3 * (time.perf_counter() - t0) / args.steps, 4)}
+            dsolver.close()
+        depth[f"full_{info['levels']}_levels"] = {"iterations": res["iterations"], "ms_per_solve": round(ms_per_step, 4)}
+        out["depth_ablation"] = depth
+        log("depth ablation:", json.dumps(depth))
 
         # supernode hierarchy rebuilt on the device from the analysed pattern
         # (Sec. 4.1): the step repeated when contacts change the pattern
