@@ -488,9 +488,20 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
 #pragma unroll
         for (int j = 0; j < kPreLevels; ++j)
             if (u[j] >= 0) acc += ycor[j];
-        for (int l = kPreLevels + 1; l < v.L; ++l) {
-            const int uu = v.anc[static_cast<long long>(l - 1) * v.NS + slot];
-            if (uu >= 0) acc += v.y[l][3 * uu + c];
+        if (v.L > kPreLevels + 1) {
+            // deeper hierarchies: the remaining levels' unit ids at once, then
+            // their corrections at once
+            constexpr int kRest = kMaxLv - 1 - kPreLevels;
+            int ur[kRest];
+#pragma unroll
+            for (int j = 0; j < kRest; ++j)
+                ur[j] = kPreLevels + 1 + j < v.L ? v.anc[static_cast<long long>(kPreLevels + j) * v.NS + slot] : -1;
+            double yr[kRest];
+#pragma unroll
+            for (int j = 0; j < kRest; ++j) yr[j] = ur[j] >= 0 ? v.y[kPreLevels + 1 + j][3 * ur[j] + c] : 0.0;
+#pragma unroll
+            for (int j = 0; j < kRest; ++j)
+                if (ur[j] >= 0) acc += yr[j];
         }
         zv = acc;
         v.z[base + t] = zv;
@@ -576,25 +587,22 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
         if (q == 0 && d < nd) zs[48 * d + i] = s;
         __syncthreads();  // stage free for the next pair
     }
-    // the corrections of the slot (prolongation), loaded after the rounds:
-    // registers held through them would cost a workgroup per CU
-    int u[kPreLevels];
+    // the corrections of the slot (prolongation) at every coarse level,
+    // loaded after the rounds (registers held through them would cost a
+    // workgroup per CU): all unit ids at once, then all corrections at once
+    int u[kMaxLv - 1];
 #pragma unroll
-    for (int j = 0; j < kPreLevels; ++j)
+    for (int j = 0; j < kMaxLv - 1; ++j)
         u[j] = (live && j + 1 < v.L) ? v.anc[static_cast<long long>(j) * v.NS + slot] : -1;
-    double ycor[kPreLevels];
+    double ycor[kMaxLv - 1];
 #pragma unroll
-    for (int j = 0; j < kPreLevels; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
+    for (int j = 0; j < kMaxLv - 1; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
     double zv = 0.0;
     if (live) {
         double acc = zs[t];
 #pragma unroll
-        for (int j = 0; j < kPreLevels; ++j)
+        for (int j = 0; j < kMaxLv - 1; ++j)
             if (u[j] >= 0) acc += ycor[j];
-        for (int l = kPreLevels + 1; l < v.L; ++l) {
-            const int uu = v.anc[static_cast<long long>(l - 1) * v.NS + slot];
-            if (uu >= 0) acc += v.y[l][3 * uu + c];
-        }
         zv = acc;
         v.z[base + t] = zv;
     }
