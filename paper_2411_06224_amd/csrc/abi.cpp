@@ -23,7 +23,7 @@ struct Layout {
     size_t total = 0;
     size_t remap, map, perm_src, perm_full, rp0, ci0, lead1, anc, g_u1, srp, sci, srow, tptr, tidx;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
-    size_t ganc[kMaxLv], gpos[kMaxLv], gmask[kMaxLv], cp_ptr[kMaxLv], lmask;
+    size_t ganc, gpos, gmask, cp_ptr[kMaxLv], lmask;
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
     size_t b, x, r, z, p0, p1, q, r1, y[kMaxLv], cpart, P_sigma, P_rr, P_bb, P_rho0, P_rho1, st, flag;
     size_t inverse_bytes = 0;
@@ -57,6 +57,8 @@ struct mas_handle {
     Plan plan;
     Layout lay;
     std::vector<std::vector<int>> translated;  // level-1 reduction sources and level-0 domain blocks in caller order
+    std::vector<int> gtab_i;                   // restriction tables of levels >= 2 as uploaded ([G][L-2][W1]):
+    std::vector<uint64_t> gtab_m;              // ancestors then writer positions; writer masks
     char* ws = nullptr;
     size_t ws_size = 0;
     char* uploaded_to = nullptr;
@@ -144,6 +146,10 @@ void make_layout(mas_handle* h) {
     Y.lmask = Y.take(sizeof(uint64_t) * P.NS);
     Y.anc = Y.take(I * P.anc.size());
     Y.g_u1 = Y.take(I * P.g_u1.size());
+    const size_t gtab = P.L > 2 ? static_cast<size_t>(P.G) * (P.L - 2) * P.W1 : 0;  // [G][L-2][W1]
+    Y.ganc = Y.take(I * gtab);
+    Y.gpos = Y.take(I * gtab);
+    Y.gmask = Y.take(sizeof(uint64_t) * gtab);
     if (P.sym) {
         Y.srp = Y.take(I * P.srp.size());
         Y.sci = Y.take(I * P.sci.size());
@@ -159,12 +165,7 @@ void make_layout(mas_handle* h) {
         Y.dom_ptr[l] = Y.take(I * P.dom_ptr[l].size());
         Y.dom_blk[l] = Y.take(I * P.dom_blk[l].size());
         Y.dom_ab[l] = Y.take(I * P.dom_ab[l].size());
-        if (l >= 2) {
-            Y.ganc[l] = Y.take(I * P.ganc[l].size());
-            Y.gpos[l] = Y.take(I * P.gpos[l].size());
-            Y.gmask[l] = Y.take(sizeof(uint64_t) * P.gmask[l].size());
-            Y.cp_ptr[l] = Y.take(I * P.cp_ptr[l].size());
-        }
+        if (l >= 2) Y.cp_ptr[l] = Y.take(I * P.cp_ptr[l].size());
     }
     Y.H64 = Y.take(Dd * 9 * nsb);
     Y.H32 = mixed ? Y.take(F * 9 * static_cast<size_t>(P.nnzb)) : 0;
@@ -227,15 +228,13 @@ SolverView view(const mas_handle* h) {
         v.ndom[l] = P.ndom[l];
         v.inv64[l] = at<double>(h, Y.inv64[l]);
         v.inv32[l] = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.inv32[l]) : nullptr;
-        if (l >= 2) {
-            v.ganc[l] = at<int>(h, Y.ganc[l]);
-            v.gpos[l] = at<int>(h, Y.gpos[l]);
-            v.gmask[l] = at<uint64_t>(h, Y.gmask[l]);
-            v.cp_ptr[l] = at<int>(h, Y.cp_ptr[l]);
-        }
+        if (l >= 2) v.cp_ptr[l] = at<int>(h, Y.cp_ptr[l]);
         if (l >= 1) v.y[l] = at<double>(h, Y.y[l]);
     }
     v.g_u1 = at<int>(h, Y.g_u1);
+    v.ganc = at<int>(h, Y.ganc);
+    v.gpos = at<int>(h, Y.gpos);
+    v.gmask = at<uint64_t>(h, Y.gmask);
     v.cpart = at<double>(h, Y.cpart);
     v.P_sigma = at<double>(h, Y.P_sigma);
     v.P_rr = at<double>(h, Y.P_rr);
@@ -327,13 +326,27 @@ int upload_plan(mas_handle* h, hipStream_t s) {
         HIP_TRY(put(Y.dom_ptr[l], P.dom_ptr[l]));
         HIP_TRY(put(Y.dom_blk[l], l == 0 ? h->translated[1] : P.dom_blk[l]));
         HIP_TRY(put(Y.dom_ab[l], P.dom_ab[l]));
-        if (l >= 2) {
-            HIP_TRY(put(Y.ganc[l], P.ganc[l]));
-            HIP_TRY(put(Y.gpos[l], P.gpos[l]));
-            HIP_TRY(hipMemcpyAsync(h->ws + Y.gmask[l], P.gmask[l].data(), sizeof(uint64_t) * P.gmask[l].size(),
-                                   hipMemcpyHostToDevice, s));
-            HIP_TRY(put(Y.cp_ptr[l], P.cp_ptr[l]));
-        }
+        if (l >= 2) HIP_TRY(put(Y.cp_ptr[l], P.cp_ptr[l]));
+    }
+    if (P.L > 2) {
+        // the per-level [G][W1] tables interleaved to [G][L-2][W1]: one
+        // contiguous row per group
+        const int W = P.W1, nl = P.L - 2;
+        const size_t gtab = static_cast<size_t>(P.G) * nl * W;
+        h->gtab_i.assign(2 * gtab, -1);
+        h->gtab_m.assign(gtab, 0);
+        for (int g = 0; g < P.G; ++g)
+            for (int l = 2; l < P.L; ++l)
+                for (int i = 0; i < W; ++i) {
+                    const size_t src = static_cast<size_t>(g) * W + i;
+                    const size_t dst = (static_cast<size_t>(g) * nl + (l - 2)) * W + i;
+                    h->gtab_i[dst] = P.ganc[l][src];
+                    h->gtab_i[gtab + dst] = P.gpos[l][src];
+                    h->gtab_m[dst] = P.gmask[l][src];
+                }
+        HIP_TRY(hipMemcpyAsync(h->ws + Y.ganc, h->gtab_i.data(), sizeof(int) * gtab, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->ws + Y.gpos, h->gtab_i.data() + gtab, sizeof(int) * gtab, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->ws + Y.gmask, h->gtab_m.data(), sizeof(uint64_t) * gtab, hipMemcpyHostToDevice, s));
     }
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors are pageable
     return MAS_OK;

@@ -91,11 +91,21 @@ __device__ inline double sum_partials(const double* __restrict__ p, int n, doubl
 
 __device__ inline bool finite(double x) { return x - x == 0.0; }
 
+// Ends a kernel's block of early loads: an empty statement that the compiler
+// must treat as touching memory, so that it keeps those loads in the order
+// written, ahead of this point, instead of sinking each one into the branch
+// that first uses it (behind the others).  It emits no instruction.
+__device__ __forceinline__ void keep_loads_issued() { asm volatile("" ::: "memory"); }
+
 // sum_partials split in two, so that the loads can be issued early and their
 // latency overlap other loads: partials_load() fetches thread t's bucket
 // entries p[t], p[t + 256], ... into registers (n <= 1024), partials_sum()
 // adds them in sum_partials' order (same bits) and folds the buckets.  For
-// n > 1024 partials_sum() falls back to sum_partials.
+// n > 1024 partials_sum() falls back to sum_partials.  Every thread issues
+// its four loads unconditionally, at indices clamped to [0, n) (n >= 1), so
+// that no branch separates them from the loads issued after them and a wait
+// for them need not wait for those too; partials_sum() reads only the
+// entries below n.
 struct PartialLoads {
     double v[4];
 };
@@ -105,8 +115,7 @@ __device__ inline PartialLoads partials_load(const double* __restrict__ p, int n
     const int t = threadIdx.x;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int i = t + 256 * j;
-        L.v[j] = (t < 256 && i < n && n <= 1024) ? p[i] : 0.0;
+        L.v[j] = p[min(t + 256 * j, n - 1)];
     }
     return L;
 }
@@ -114,7 +123,7 @@ __device__ inline PartialLoads partials_load(const double* __restrict__ p, int n
 __device__ inline double partials_sum(const PartialLoads& L, const double* __restrict__ p, int n, double* buf) {
     if (n > 1024) return sum_partials(p, n, buf);
     const int t = threadIdx.x;
-    if (t < 256) {
+    if (t < 256) {  // as in partials_load: bucket t holds p[t], p[t + 256], ... below n
         double s = 0.0;
         if (t + 768 < n) {
             s += (L.v[0] + L.v[1]) + (L.v[2] + L.v[3]);

@@ -57,10 +57,11 @@ struct SolverView {
     const int* anc;       // [(L-1)*NS]
     const int* g_u1;      // [G+1]
     int W1;                       // restriction: most level-1 units in a group
-    const int* ganc[kMaxLv];      // l >= 2: [G * W1] level-l unit of each level-1 unit of each group (-1 pad)
-    const int* gpos[kMaxLv];      // l >= 2: [G * W1] its partial position, -1 if it writes none
+    // levels l >= 2, [G][L-2][W1] (entry (g, l - 2, i) for level-1 unit i of group g, -1 / 0 pad):
+    const int* ganc;              // its level-l unit
+    const int* gpos;              // its partial position, -1 if it writes none
+    const uint64_t* gmask;        // writers: group-local level-1 units below it
     const uint64_t* lmask;        // [NS] leader slots: lanes of the domain in the slot's level-1 unit
-    const uint64_t* gmask[kMaxLv];  // l >= 2: [G * W1] writers: group-local level-1 units below it
     const int* cp_ptr[kMaxLv];    // l >= 2: [S_l + 1]
     // stored slot-ordered matrix (9 planes: H64 of nsb, H32 of nnzb values)
     double* H64;

@@ -1,9 +1,11 @@
 // Restriction of a residual to the coarse levels (C_l r of Supp. Eq. 6),
 // computed by the workgroup that owns a group of level-0 domains.
 //
-// restrict_prefetch() issues every plan load of the group at once (no
-// barrier), so its latency overlaps whatever the kernel does next;
-// restrict_group() then works from shared memory only.
+// restrict_load() issues every plan load of the group at once into
+// registers, and restrict_stage() writes them to shared memory later, just
+// before the barrier that publishes the residual: the loads' latency overlaps
+// whatever the kernel does in between, and no wait for them sits on the
+// kernel's early path.  restrict_group() then works from shared memory only.
 #pragma once
 
 #include "launch.hpp"
@@ -44,33 +46,81 @@ struct GroupUnits {
     int lo, n;
 };
 
-// Loads the group's plan (level-1 unit and writer flag of every slot, and
-// for every level l >= 2 the ancestor and writer position of every level-1
-// unit of the group, from the per-group padded tables, so that no load
-// waits for another) into shared memory.  Needs a barrier before use.
-// Returns the group's level-1 unit range for restrict_group.
-__device__ inline GroupUnits restrict_prefetch(const SolverView& v, int g, double* sm) {
-    if (v.L < 2) return GroupUnits{0, 0};
-    const RestrictSmem S = restrict_layout(v, sm);
-    const int RG = v.RG, W = v.W1, slot0 = g * RG;
-    const int u1_lo = v.g_u1[g], n1 = v.g_u1[g + 1] - u1_lo;
-    for (int i = threadIdx.x; i < RG; i += blockDim.x) {
-        const int slot = slot0 + i;
-        const bool in = slot < v.NS;
-        S.up0[i] = in ? v.anc[slot] : -1;
-        S.lead[i] = in ? v.lead1[slot] : -1;
-        S.lmask[i] = in ? v.lmask[slot] : 0;
+// Plan entries a thread holds in registers between restrict_load and
+// restrict_stage: its slot's entries and kPlanRegs entries of the group's
+// level >= 2 table; a larger table's remainder is loaded by restrict_stage.
+constexpr int kPlanRegs = 1;
+
+struct RestrictLoads {
+    GroupUnits gu;
+    int up0, lead;  // raw loads at clamped indices: restrict_stage drops the
+    uint64_t lmask; // ones outside the group's slots and table row
+    int anc[kPlanRegs], pos[kPlanRegs];
+    uint64_t gm[kPlanRegs];
+};
+
+// Issues the loads of the group's plan: level-1 unit, writer flag and member
+// mask of every slot, and for every level l >= 2 the ancestor, writer
+// position and writer mask of every level-1 unit of the group (entry
+// (l - 2) W1 + i of the group's row of the level-major tables, so that the
+// whole row is one coalesced range and no load waits for another).  One
+// slot per thread: RG = D0 N <= 128 and every kernel that restricts runs at
+// least 256 threads.  The loads are issued unconditionally, at clamped
+// indices (arrays of NS entries stand in for tables a shallow hierarchy does
+// not have), so that no branch separates them from the loads issued before
+// them and a wait for those need not wait for these too.
+__device__ inline RestrictLoads restrict_load(const SolverView& v, int g) {
+    RestrictLoads R;
+    const int t = threadIdx.x;
+    const bool lv1 = v.L >= 2, lv2 = v.L > 2;
+    const int u1_lo = v.g_u1[g];
+    R.gu = lv1 ? GroupUnits{u1_lo, v.g_u1[g + 1] - u1_lo} : GroupUnits{0, 0};
+    const int sc = min(g * v.RG + t, v.NS - 1);
+    R.up0 = (lv1 ? v.anc : v.lead1)[sc];
+    R.lead = v.lead1[sc];
+    R.lmask = v.lmask[sc];
+    const int tot = lv2 ? (v.L - 2) * v.W1 : 0;
+    const long long row = static_cast<long long>(g) * tot;
+    const long long last = lv2 ? static_cast<long long>(v.G) * tot - 1 : 0;
+#pragma unroll
+    for (int j = 0; j < kPlanRegs; ++j) {
+        const long long e = min(row + t + j * static_cast<int>(blockDim.x), last);
+        R.anc[j] = (lv2 ? v.ganc : v.lead1)[e];
+        R.pos[j] = (lv2 ? v.gpos : v.lead1)[e];
+        R.gm[j] = (lv2 ? v.gmask : v.lmask)[e];
     }
-    if (v.L > 2) {
-        const int tot = (v.L - 2) * W;
-        for (int o = threadIdx.x; o < tot; o += blockDim.x) {
-            const int l = 2 + o / W, i = o - (l - 2) * W;
-            S.anc[o] = v.ganc[l][static_cast<long long>(g) * W + i];
-            S.pos[o] = v.gpos[l][static_cast<long long>(g) * W + i];
-            S.gmask[o] = v.gmask[l][static_cast<long long>(g) * W + i];
+    return R;
+}
+
+// Writes the loaded plan to shared memory (needs a barrier before
+// restrict_group) and returns the group's level-1 unit range.
+__device__ inline GroupUnits restrict_stage(const SolverView& v, int g, const RestrictLoads& R, double* sm) {
+    if (v.L < 2) return R.gu;
+    const RestrictSmem S = restrict_layout(v, sm);
+    const int t = threadIdx.x;
+    if (t < v.RG) {
+        const bool in = g * v.RG + t < v.NS;
+        S.up0[t] = in ? R.up0 : -1;
+        S.lead[t] = in ? R.lead : -1;
+        S.lmask[t] = in ? R.lmask : 0;
+    }
+    const int tot = (v.L - 2) * v.W1;
+#pragma unroll
+    for (int j = 0; j < kPlanRegs; ++j) {
+        const int o = t + j * static_cast<int>(blockDim.x);
+        if (o < tot) {
+            S.anc[o] = R.anc[j];
+            S.pos[o] = R.pos[j];
+            S.gmask[o] = R.gm[j];
         }
     }
-    return GroupUnits{u1_lo, n1};
+    const long long row = static_cast<long long>(g) * tot;
+    for (int o = t + kPlanRegs * static_cast<int>(blockDim.x); o < tot; o += blockDim.x) {
+        S.anc[o] = v.ganc[row + o];
+        S.pos[o] = v.gpos[row + o];
+        S.gmask[o] = v.gmask[row + o];
+    }
+    return R.gu;
 }
 
 // rs[3*RG]: the group's residual in slot order (zero on slots >= NS), and

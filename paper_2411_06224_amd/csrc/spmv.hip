@@ -156,6 +156,7 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
 // are gathered through X; tl: the group's transposed entries (LDS).
 constexpr int kSymChunk = 512;
 constexpr int kSymPlane = kSymChunk + kPad;
+constexpr int kTlRegs = 4;  // transposed-list entries a thread loads ahead (a longer list's rest is loaded late)
 
 template <typename T, typename X>
 __device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restrict__ H, X xg, const double* xs,
@@ -260,21 +261,24 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     const int nown = 3 * (r1 - r0);
-    // every independent load before the first barrier
+    // every independent load before the first wait: the rho partials first
+    // (needed first; loads complete in issue order), then the group's own
+    // entries of z and p_{k-1}, unconditionally at clamped indices (see
+    // partials_load)
+    const double* Prho = v.P_rho[(k - 1) & 1];
+    const PartialLoads rl = partials_load(Prho, v.G);
     const double* pold = k > 1 ? v.p[(k - 1) & 1] : v.z;  // k = 1: p_1 = z_0 (+ 0 * z_0)
     double zo[2], po[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int o = t + q * kThreads;
-        zo[q] = po[q] = 0.0;
-        if (o < nown) {
-            zo[q] = v.z[3LL * r0 + o];
-            po[q] = pold[3LL * r0 + o];
-        }
+        const long long e = 3LL * r0 + min(t + q * kThreads, nown - 1);
+        zo[q] = v.z[e];
+        po[q] = pold[e];
     }
+    keep_loads_issued();
     // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
     const double rk2 = v.st->rho[k & 1];
-    const double rk1 = sum_partials(v.P_rho[(k - 1) & 1], v.G, buf);
+    const double rk1 = partials_sum(rl, Prho, v.G, buf);
     if (g == 0 && t == 0) v.st->rho[(k - 1) & 1] = rk1;
     const double beta = k > 1 ? rk1 / rk2 : 0.0;
     double* pk = v.p[k & 1];
@@ -321,24 +325,35 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     const int nown = 3 * (r1 - r0);
     double* xs = dyn;
     int* tl = reinterpret_cast<int*>(dyn + 3 * v.RG);
-    // every independent load before the first barrier
+    // every independent load before the first wait: the rho partials first
+    // (needed first; loads complete in issue order), then the group's own
+    // entries of z and p_{k-1} and its transposed-entry list, all
+    // unconditionally at clamped indices (see partials_load); the list goes
+    // to LDS only after the rho sum
+    const double* Prho = v.P_rho[(k - 1) & 1];
+    const PartialLoads rl = partials_load(Prho, v.G);
     const double* pold = k > 1 ? v.p[(k - 1) & 1] : v.z;  // k = 1: p_1 = z_0 (+ 0 * z_0)
     double zo[2], po[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int o = t + q * kThreads;
-        zo[q] = po[q] = 0.0;
-        if (o < nown) {
-            zo[q] = v.z[3LL * r0 + o];
-            po[q] = pold[3LL * r0 + o];
-        }
+        const long long e = 3LL * r0 + min(t + q * kThreads, nown - 1);
+        zo[q] = v.z[e];
+        po[q] = pold[e];
     }
     const int tb0 = v.tptr[r0], tn = v.tptr[r1] - tb0;
-    for (int e = t; e < tn; e += kThreads) tl[e] = v.tidx[tb0 + e];
+    const int* tsrc = tn > 0 ? v.tidx + tb0 : v.srp;  // srp: a stand-in with entries when the list is empty
+    int tlr[kTlRegs];
+#pragma unroll
+    for (int j = 0; j < kTlRegs; ++j) tlr[j] = tsrc[min(t + j * kThreads, max(tn - 1, 0))];
+    keep_loads_issued();
     const double rk2 = v.st->rho[k & 1];
     // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
-    const double rk1 = sum_partials(v.P_rho[(k - 1) & 1], v.G, buf);
+    const double rk1 = partials_sum(rl, Prho, v.G, buf);
     if (g == 0 && t == 0) v.st->rho[(k - 1) & 1] = rk1;
+#pragma unroll
+    for (int j = 0; j < kTlRegs; ++j)
+        if (t + j * kThreads < tn) tl[t + j * kThreads] = tlr[j];
+    for (int e = t + kTlRegs * kThreads; e < tn; e += kThreads) tl[e] = v.tidx[tb0 + e];
     const double beta = k > 1 ? rk1 / rk2 : 0.0;
     double* pk = v.p[k & 1];
     double pv[2];
@@ -380,7 +395,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     double acc[2];
-    const GroupUnits gu = restrict_prefetch(v, g, dyn + 3 * v.RG);
+    const RestrictLoads pl = restrict_load(v, g);
     if constexpr (kSym) {
         double* xs = dyn + 3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L);
         int* tl = reinterpret_cast<int*>(xs + 3 * v.RG);
@@ -411,7 +426,8 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
             rs[o] = e;
         }
     }
-    rr = block_sum(rr, scratch);  // its barriers also publish rs
+    const GroupUnits gu = restrict_stage(v, g, pl, dyn + 3 * v.RG);
+    rr = block_sum(rr, scratch);  // its barriers also publish rs and the plan
     if (kMode == kResidInit) bb = block_sum(bb, scratch);
     if (threadIdx.x == 0) {
         v.P_rr[g] = rr;

@@ -86,18 +86,18 @@ __global__ void k_init_rhs(SolverView v) {
     double* rs = sm;
     double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L);
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
-    const GroupUnits gu = restrict_prefetch(v, g, sm + 3 * v.RG);
     const long long i = 3LL * g * v.RG + t;
     double bv = 0.0;
-    if (t < 3 * v.RG) {
-        if (i < 3LL * v.NS) {
-            bv = v.b[i];
-            v.r[i] = bv;
-            v.x[i] = 0.0;
-        }
-        rs[t] = bv;
+    const bool own = t < 3 * v.RG && i < 3LL * v.NS;
+    if (own) bv = v.b[i];
+    const RestrictLoads pl = restrict_load(v, g);
+    if (own) {
+        v.r[i] = bv;
+        v.x[i] = 0.0;
     }
-    const double bb = block_sum(bv * bv, scratch);
+    if (t < 3 * v.RG) rs[t] = bv;
+    const GroupUnits gu = restrict_stage(v, g, pl, sm + 3 * v.RG);
+    const double bb = block_sum(bv * bv, scratch);  // its barriers also publish rs and the plan
     if (t == 0) {
         v.P_rr[g] = bb;
         v.P_bb[g] = bb;
@@ -115,20 +115,17 @@ __global__ void k_update(SolverView v, int k) {
     double* scratch = sm + 3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L);
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
     // issue every independent load (the stop flag's included) before the
-    // first wait; after a stop nothing is written
-    const long long i = 3LL * g * v.RG + t;
-    const bool own = t < 3 * v.RG && i < 3LL * v.NS;
-    const double* pk = v.p[k & 1];
-    double xv = 0.0, pv = 0.0, rv0 = 0.0, qv = 0.0;
-    if (own) {
-        xv = v.x[i];
-        pv = pk[i];
-        rv0 = v.r[i];
-        qv = v.q[i];
-    }
+    // first wait, the partials of sigma first (they are needed first, and
+    // loads complete in issue order); after a stop nothing is written
     const PartialLoads sig = partials_load(v.P_sigma, v.G);
     const double rho = v.st->rho[(k - 1) & 1];
-    const GroupUnits gu = restrict_prefetch(v, g, sm + 3 * v.RG);
+    const long long i = 3LL * g * v.RG + t;
+    const bool own = t < 3 * v.RG && i < 3LL * v.NS;
+    const long long ic = own ? i : 0;  // unconditional loads (see partials_load)
+    const double* pk = v.p[k & 1];
+    const double xv = v.x[ic], pv = pk[ic], rv0 = v.r[ic], qv = v.q[ic];
+    const RestrictLoads pl = restrict_load(v, g);
+    keep_loads_issued();
     if (v.st->done) return;
     const double sigma = partials_sum(sig, v.P_sigma, v.G, scratch);
     if (!(sigma > 0.0) || !finite(sigma) || !finite(rho)) {
@@ -147,6 +144,7 @@ __global__ void k_update(SolverView v, int k) {
         v.r[i] = rv;
     }
     if (t < 3 * v.RG) rs[t] = rv;
+    const GroupUnits gu = restrict_stage(v, g, pl, sm + 3 * v.RG);
     const double rr = block_sum(rv * rv, scratch);  // its barriers also publish rs and the plan
     if (t == 0) v.P_rr[g] = rr;
     restrict_group(v, gu, rs, sm + 3 * v.RG);
@@ -157,9 +155,11 @@ __global__ void k_restrict(SolverView v) {
     extern __shared__ double sm[];
     double* rs = sm;
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
-    const GroupUnits gu = restrict_prefetch(v, g, sm + 3 * v.RG);
     const long long i = 3LL * g * v.RG + t;
-    if (t < 3 * v.RG) rs[t] = i < 3LL * v.NS ? v.r[i] : 0.0;
+    const double rv = (t < 3 * v.RG && i < 3LL * v.NS) ? v.r[i] : 0.0;
+    const RestrictLoads pl = restrict_load(v, g);
+    if (t < 3 * v.RG) rs[t] = rv;
+    const GroupUnits gu = restrict_stage(v, g, pl, sm + 3 * v.RG);
     __syncthreads();
     restrict_group(v, gu, rs, sm + 3 * v.RG);
 }
