@@ -94,7 +94,10 @@ __device__ inline bool finite(double x) { return x - x == 0.0; }
 // Ends a kernel's block of early loads: an empty statement that the compiler
 // must treat as touching memory, so that it keeps those loads in the order
 // written, ahead of this point, instead of sinking each one into the branch
-// that first uses it (behind the others).  It emits no instruction.
+// that first uses it (behind the others).  It emits no instruction.  Uniform
+// values (the stop flag) are read before it: after it the compiler no longer
+// takes them for unchanged memory and reads them with a vector load, whose
+// wait would then cover every load issued before.
 __device__ __forceinline__ void keep_loads_issued() { asm volatile("" ::: "memory"); }
 
 // sum_partials split in two, so that the loads can be issued early and their

@@ -310,7 +310,6 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
         if (mode != kApplyPlain) convergence_decision(v, mode, k, tol, flags, buf);
         return;
     }
-    if (mode == kApplyIter && v.st->done) return;
     const int gb = blockIdx.x - 1;
     int l = 1;
     while (l + 1 < v.L && gb >= tab.off[l + 1]) ++l;
@@ -340,6 +339,11 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
             }
         }
     }
+    // the stop flag is read once the inverse loads are in flight; after a
+    // stop nothing is written
+    const int stop = v.st->done;
+    keep_loads_issued();
+    if (mode == kApplyIter && stop) return;
     if (l == 1) {
         if (t < n) rl[t] = t < 3 * nu ? v.r1[3 * u0 + t] : 0.0;
     } else if constexpr (kN == 16) {
@@ -449,7 +453,6 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
     const int N = kN > 0 ? kN : v.N;
     const int n = 3 * N;
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
-    if (kMode != kApplyPlain && v.st->done) return;
     const int nd = min(v.D0, v.M - g * v.D0);  // domains of this group
     const bool live = t < nd * n;
     const long long base = 3LL * g * v.RG;
@@ -461,6 +464,11 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
     for (int j = 0; j < kPreLevels; ++j)
         u[j] = (live && j + 1 < v.L) ? v.anc[static_cast<long long>(j) * v.NS + slot] : -1;
     const double rv = live ? v.r[base + t] : 0.0;
+    // the stop flag is read once these loads are in flight; after a stop
+    // nothing is written
+    const int stop = v.st->done;
+    keep_loads_issued();
+    if (kMode != kApplyPlain && stop) return;
     double ycor[kPreLevels];
 #pragma unroll
     for (int j = 0; j < kPreLevels; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
@@ -532,7 +540,6 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
     __shared__ TI stage[kPairs * kPacked];
     __shared__ double red[8];
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
-    if (kMode != kApplyPlain && v.st->done) return;
     const int nd = min(v.D0, v.M - g * v.D0);  // domains of this group
     const bool live = t < nd * 48;
     const long long base = 3LL * g * v.RG;
@@ -557,6 +564,11 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
     };
     fetch(0);
     const double rv = live ? v.r[base + t] : 0.0;
+    // the stop flag is read once these loads are in flight; after a stop
+    // nothing is written
+    const int stop = v.st->done;
+    keep_loads_issued();
+    if (kMode != kApplyPlain && stop) return;
     if (t < 384) rs[t] = rv;
     const int row = t >> 2, q = t & 3;  // 96 rows of a pair, four quarters each
     const int dl = row / 48, i = row - 48 * dl;

@@ -256,7 +256,6 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     __shared__ double prod[3 * kPlane];
     __shared__ double buf[256];
     __shared__ double xs[384];
-    if (v.st->done) return;
     const int t = threadIdx.x;
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
@@ -275,7 +274,9 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
         zo[q] = v.z[e];
         po[q] = pold[e];
     }
+    const int stop = v.st->done;
     keep_loads_issued();
+    if (stop) return;  // after a stop nothing is written
     // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
     const double rk2 = v.st->rho[k & 1];
     const double rk1 = partials_sum(rl, Prho, v.G, buf);
@@ -318,7 +319,6 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     __shared__ double prod[6 * kSymPlane];
     __shared__ double buf[256];
     extern __shared__ double dyn[];  // xs[3 RG] doubles + tl[maxT] ints
-    if (v.st->done) return;
     const int t = threadIdx.x;
     const int g = xcd_group(blockIdx.x, v.G);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
@@ -345,7 +345,9 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     int tlr[kTlRegs];
 #pragma unroll
     for (int j = 0; j < kTlRegs; ++j) tlr[j] = tsrc[min(t + j * kThreads, max(tn - 1, 0))];
+    const int stop = v.st->done;
     keep_loads_issued();
+    if (stop) return;  // after a stop nothing is written
     const double rk2 = v.st->rho[k & 1];
     // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
     const double rk1 = partials_sum(rl, Prho, v.G, buf);

@@ -125,8 +125,9 @@ __global__ void k_update(SolverView v, int k) {
     const double* pk = v.p[k & 1];
     const double xv = v.x[ic], pv = pk[ic], rv0 = v.r[ic], qv = v.q[ic];
     const RestrictLoads pl = restrict_load(v, g);
+    const int stop = v.st->done;
     keep_loads_issued();
-    if (v.st->done) return;
+    if (stop) return;
     const double sigma = partials_sum(sig, v.P_sigma, v.G, scratch);
     if (!(sigma > 0.0) || !finite(sigma) || !finite(rho)) {
         if (g == 0 && t == 0) {
