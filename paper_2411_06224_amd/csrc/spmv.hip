@@ -86,14 +86,36 @@ struct XDir {
     __device__ __forceinline__ double at(int i) const { return __fma_rn(beta, p[i], z[i]); }
 };
 
+// Column indices of this thread's blocks t, t + 256, ... of the chunk
+// starting at cs, loaded one chunk ahead of their use so that a chunk's
+// gathers need not wait for them.  The loads are unconditional, at indices
+// clamped to the range's last block (none for an empty range).
+constexpr int kRowPer = kChunk / kThreads;
+
+struct ChunkCols {
+    int j[kRowPer];
+};
+
+__device__ __forceinline__ ChunkCols chunk_cols(const int* __restrict__ ci, int cs, int ke) {
+    ChunkCols c;
+#pragma unroll
+    for (int kk = 0; kk < kRowPer; ++kk) c.j[kk] = 0;
+    if (cs < ke) {
+#pragma unroll
+        for (int kk = 0; kk < kRowPer; ++kk) c.j[kk] = ci[min(cs + static_cast<int>(threadIdx.x) + kk * kThreads, ke - 1)];
+    }
+    return c;
+}
+
 // Row sums of rows [r0, r1) of H x.  Owner o = 3 (row - r0) + c is thread
 // o (acc[0]) or o - 256 (acc[1]); 3 (r1 - r0) <= 512.  prod: 3 * kPlane LDS.
 // kLds: x of the columns r0 .. r1 - 1 is read from xs (LDS), the others
-// through X.
+// through X.  first: chunk_cols(ci, rp[r0], rp[r1]), which the caller may
+// load early.
 template <typename T, bool kPlanar, typename X, bool kLds = false>
 __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const int* __restrict__ ci,
                                             Blocks<T, kPlanar> H, X x, int r0, int r1, double* prod,
-                                            double (&acc)[2], const double* xs = nullptr) {
+                                            double (&acc)[2], const ChunkCols& first, const double* xs = nullptr) {
     const int t = threadIdx.x;
     const int nown = 3 * (r1 - r0);
     int rb[2], re[2];
@@ -109,11 +131,15 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
         }
     }
     const int kb = rp[r0], ke = rp[r1];
+    ChunkCols nc = first;
     for (int cs = kb; cs < ke; cs += kChunk) {
         const int ce = min(cs + kChunk, ke);
-#pragma unroll 8
-        for (int k = cs + t; k < ce; k += kThreads) {
-            const int j = ci[k];
+        const ChunkCols cc = nc;
+#pragma unroll
+        for (int kk = 0; kk < kRowPer; ++kk) {
+            const int k = cs + t + kk * kThreads;
+            if (k >= ce) break;
+            const int j = cc.j[kk];
             double x0, x1, x2;
             const int jl = j - r0;
             if (kLds && jl >= 0 && jl < r1 - r0) {
@@ -130,6 +156,7 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
             prod[kPlane + e] = H.at(k, 3) * x0 + H.at(k, 4) * x1 + H.at(k, 5) * x2;
             prod[2 * kPlane + e] = H.at(k, 6) * x0 + H.at(k, 7) * x1 + H.at(k, 8) * x2;
         }
+        nc = chunk_cols(ci, cs + kChunk, ke);  // the next chunk's columns, in flight through the sums
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -157,10 +184,34 @@ __device__ __forceinline__ void stream_rows(const int* __restrict__ rp, const in
 constexpr int kSymChunk = 512;
 constexpr int kSymPlane = kSymChunk + kPad;
 constexpr int kTlRegs = 4;  // transposed-list entries a thread loads ahead (a longer list's rest is loaded late)
+constexpr int kSymPer = kSymChunk / kThreads;
+
+// Column slot and local row of this thread's stored blocks t, t + 256, ...
+// of the chunk starting at cs, loaded one chunk ahead (as chunk_cols).
+struct SymCols {
+    int j[kSymPer];
+    int r[kSymPer];
+};
+
+__device__ __forceinline__ SymCols sym_cols(const SolverView& v, int cs, int ke) {
+    SymCols c;
+#pragma unroll
+    for (int kk = 0; kk < kSymPer; ++kk) c.j[kk] = c.r[kk] = 0;
+    if (cs < ke) {
+#pragma unroll
+        for (int kk = 0; kk < kSymPer; ++kk) {
+            const int k = min(cs + static_cast<int>(threadIdx.x) + kk * kThreads, ke - 1);
+            c.j[kk] = v.sci[k];
+            c.r[kk] = v.srow[k];
+        }
+    }
+    return c;
+}
 
 template <typename T, typename X>
 __device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restrict__ H, X xg, const double* xs,
-                                           const int* tl, int tb0, int r0, int r1, double* prod, double (&acc)[2]) {
+                                           const int* tl, int tb0, int r0, int r1, double* prod, double (&acc)[2],
+                                           const SymCols& first) {
     const int t = threadIdx.x;
     const int nown = 3 * (r1 - r0), rows = r1 - r0;
     const long long st = v.nsb;
@@ -179,12 +230,16 @@ __device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restr
         }
     }
     const int kb = v.srp[r0], ke = v.srp[r1];
+    SymCols nc = first;
     for (int cs = kb; cs < ke; cs += kSymChunk) {
         const int ce = min(cs + kSymChunk, ke);
-#pragma unroll 4
-        for (int k = cs + t; k < ce; k += kThreads) {
-            const int j = v.sci[k];
-            const int r = v.srow[k];
+        const SymCols cc = nc;
+#pragma unroll
+        for (int kk = 0; kk < kSymPer; ++kk) {
+            const int k = cs + t + kk * kThreads;
+            if (k >= ce) break;
+            const int j = cc.j[kk];
+            const int r = cc.r[kk];
             const int jl = j - r0;
             const bool internal = jl >= 0 && jl < rows;
             double x0, x1, x2;
@@ -213,6 +268,7 @@ __device__ __forceinline__ void stream_sym(const SolverView& v, const T* __restr
                 prod[5 * kSymPlane + e] = h2 * y0 + h5 * y1 + h8 * y2;
             }
         }
+        nc = sym_cols(v, cs + kSymChunk, ke);  // the next chunk's columns, in flight through the sums
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -236,7 +292,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* _
     const int r0 = blockIdx.x * kUserRows;
     const int r1 = min(r0 + kUserRows, n_rows);
     double acc[2];
-    stream_rows<T, false>(rp, ci, Blocks<T, false>{val, 0}, XVec{x}, r0, r1, prod, acc);
+    stream_rows<T, false>(rp, ci, Blocks<T, false>{val, 0}, XVec{x}, r0, r1, prod, acc,
+                          chunk_cols(ci, rp[r0], rp[r1]));
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int o = threadIdx.x + q * kThreads;
@@ -274,6 +331,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
         zo[q] = v.z[e];
         po[q] = pold[e];
     }
+    const ChunkCols c0 = chunk_cols(v.ci0, v.rp0[r0], v.rp0[r1]);
     const int stop = v.st->done;
     keep_loads_issued();
     if (stop) return;  // after a stop nothing is written
@@ -297,7 +355,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     __syncthreads();
     double acc[2];
     stream_rows<T, true, XDir, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, XDir{v.z, pold, beta}, r0, r1, prod,
-                                     acc, xs);
+                                     acc, c0, xs);
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -345,6 +403,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     int tlr[kTlRegs];
 #pragma unroll
     for (int j = 0; j < kTlRegs; ++j) tlr[j] = tsrc[min(t + j * kThreads, max(tn - 1, 0))];
+    const SymCols c0 = sym_cols(v, v.srp[r0], v.srp[r1]);
     const int stop = v.st->done;
     keep_loads_issued();
     if (stop) return;  // after a stop nothing is written
@@ -371,7 +430,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     }
     __syncthreads();
     double acc[2];
-    stream_sym<T>(v, H, XDir{v.z, pold, beta}, xs, tl, tb0, r0, r1, prod, acc);
+    stream_sym<T>(v, H, XDir{v.z, pold, beta}, xs, tl, tb0, r0, r1, prod, acc, c0);
     double part = 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -406,9 +465,10 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
         const int tb0 = v.tptr[r0], tn = v.tptr[r1] - tb0;
         for (int e = threadIdx.x; e < tn; e += kThreads) tl[e] = v.tidx[tb0 + e];
         __syncthreads();
-        stream_sym<double>(v, v.H64, XVec{v.x}, xs, tl, tb0, r0, r1, prod, acc);
+        stream_sym<double>(v, v.H64, XVec{v.x}, xs, tl, tb0, r0, r1, prod, acc, sym_cols(v, v.srp[r0], v.srp[r1]));
     } else {
-        stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, XVec{v.x}, r0, r1, prod, acc);
+        stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, XVec{v.x}, r0, r1, prod, acc,
+                                  chunk_cols(v.ci0, v.rp0[r0], v.rp0[r1]));
     }
     double rr = 0.0, bb = 0.0;
     double* rs = dyn;
