@@ -50,6 +50,9 @@ __device__ inline double wave_sum(double v) {
 
 // Deterministic sum over the workgroup (whole waves only); the result is
 // valid in every thread.  scratch: blockDim.x / 64 doubles of shared memory.
+// kReuse = false leaves out the closing barrier, for a caller that does not
+// write scratch again.
+template <bool kReuse = true>
 __device__ inline double block_sum(double v, double* scratch) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
@@ -59,7 +62,20 @@ __device__ inline double block_sum(double v, double* scratch) {
     __syncthreads();
     double t = 0.0;
     for (int w = 0; w < nw; ++w) t += scratch[w];
+    if (kReuse) __syncthreads();
+    return t;
+}
+
+// block_sum as a kernel's last reduction, into thread 0 only (same bits):
+// one barrier, for a scratch that no thread has used before in the kernel.
+__device__ inline double block_sum_last(double v, double* scratch) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) scratch[wave] = v;
     __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (blockDim.x >> 6); ++w) t += scratch[w];
     return t;
 }
 
@@ -123,6 +139,9 @@ __device__ inline PartialLoads partials_load(const double* __restrict__ p, int n
     return L;
 }
 
+// kReuse = false leaves out the closing barrier, for a caller whose next
+// write to buf follows another barrier.
+template <bool kReuse = true>
 __device__ inline double partials_sum(const PartialLoads& L, const double* __restrict__ p, int n, double* buf) {
     if (n > 1024) return sum_partials(p, n, buf);
     const int t = threadIdx.x;
@@ -145,11 +164,9 @@ __device__ inline double partials_sum(const PartialLoads& L, const double* __res
     }
     __syncthreads();
     const double r = buf[0];
-    __syncthreads();
+    if (kReuse) __syncthreads();
     return r;
 }
-
-
 
 inline int ceil_div(long long a, long long b) { return static_cast<int>((a + b - 1) / b); }
 inline int round_waves(int threads) { return (threads + 63) / 64 * 64; }

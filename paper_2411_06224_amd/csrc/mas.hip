@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
         v.z[base + t] = zv;
     }
     if (kMode == kApplyPlain) return;
-    const double part = block_sum(rv * zv, red);
+    const double part = block_sum_last(rv * zv, red);
     if (t == 0) v.P_rho[k & 1][g] = part;
 }
 
@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
         v.z[base + t] = zv;
     }
     if (kMode == kApplyPlain) return;
-    const double part = block_sum(rv * zv, red);
+    const double part = block_sum_last(rv * zv, red);
     if (t == 0) v.P_rho[k & 1][g] = part;
 }
 

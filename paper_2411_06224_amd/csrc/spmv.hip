@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     if (stop) return;  // after a stop nothing is written
     // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
     const double rk2 = v.st->rho[k & 1];
-    const double rk1 = partials_sum(rl, Prho, v.G, buf);
+    const double rk1 = partials_sum<false>(rl, Prho, v.G, buf);  // buf is next written after later barriers
     if (g == 0 && t == 0) v.st->rho[(k - 1) & 1] = rk1;
     const double beta = k > 1 ? rk1 / rk2 : 0.0;
     double* pk = v.p[k & 1];
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
             part += pv[q] * acc[q];
         }
     }
-    part = block_sum(part, buf);
+    part = block_sum<false>(part, buf);  // the kernel's last use of buf
     if (t == 0) v.P_sigma[g] = part;
 }
 
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     if (stop) return;  // after a stop nothing is written
     const double rk2 = v.st->rho[k & 1];
     // rho_{k-1} from the group partials; rho_{k-2} as the previous SpMV recorded it
-    const double rk1 = partials_sum(rl, Prho, v.G, buf);
+    const double rk1 = partials_sum<false>(rl, Prho, v.G, buf);  // buf is next written after later barriers
     if (g == 0 && t == 0) v.st->rho[(k - 1) & 1] = rk1;
 #pragma unroll
     for (int j = 0; j < kTlRegs; ++j)
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
             part += pv[q] * acc[q];
         }
     }
-    part = block_sum(part, buf);
+    part = block_sum<false>(part, buf);  // the kernel's last use of buf
     if (t == 0) v.P_sigma[g] = part;
 }
 

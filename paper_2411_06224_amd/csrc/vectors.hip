@@ -128,7 +128,8 @@ __global__ void k_update(SolverView v, int k) {
     const int stop = v.st->done;
     keep_loads_issued();
     if (stop) return;
-    const double sigma = partials_sum(sig, v.P_sigma, v.G, scratch);
+    // (block_sum's first barrier orders scratch's reuse)
+    const double sigma = partials_sum<false>(sig, v.P_sigma, v.G, scratch);
     if (!(sigma > 0.0) || !finite(sigma) || !finite(rho)) {
         if (g == 0 && t == 0) {
             v.st->status = (finite(sigma) && finite(rho)) ? -2 : -6;
@@ -146,7 +147,8 @@ __global__ void k_update(SolverView v, int k) {
     }
     if (t < 3 * v.RG) rs[t] = rv;
     const GroupUnits gu = restrict_stage(v, g, pl, sm + 3 * v.RG);
-    const double rr = block_sum(rv * rv, scratch);  // its barriers also publish rs and the plan
+    // its barriers also publish rs and the plan; scratch is not used again
+    const double rr = block_sum<false>(rv * rv, scratch);
     if (t == 0) v.P_rr[g] = rr;
     restrict_group(v, gu, rs, sm + 3 * v.RG);
 }
