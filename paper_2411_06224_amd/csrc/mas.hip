@@ -27,36 +27,57 @@ __device__ __forceinline__ double inv_load(const TI* p) {
 // ------------------------------------------------------------ coarse sums
 // A_l = C H C^T by levels (Supp. Eq. 5: A_(l) = C A C^T with unit 3x3
 // weights).  Each coarse block owns a list of fine blocks and sums it in a
-// fixed order: no atomics, bitwise reproducible.
+// fixed order: no atomics, bitwise reproducible.  Nine consecutive threads
+// take one coarse block, thread c summing entry c over the list in order,
+// four list entries loaded at a time (their indices, then their values), so
+// that the list's loads overlap instead of following one another.
+constexpr int kSumRound = 4;
 
 __global__ void __launch_bounds__(256) k_coarse_sum_first(int nnzA, const int* __restrict__ ptr,
                                                            const int* __restrict__ src, const double* __restrict__ Hu,
                                                            double* __restrict__ A) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= nnzA) return;
-    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int q = ptr[t]; q < ptr[t + 1]; ++q) {
-        const double* blk = Hu + 9LL * src[q];
+    const long long gt = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (gt >= 9LL * nnzA) return;
+    const int t = static_cast<int>(gt / 9), c = static_cast<int>(gt % 9);
+    const int qe = ptr[t + 1];
+    int q = ptr[t];
+    double s = 0.0;
+    for (; q + kSumRound <= qe; q += kSumRound) {
+        int i[kSumRound];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) s[c] += blk[c];
+        for (int j = 0; j < kSumRound; ++j) i[j] = src[q + j];
+        double a[kSumRound];
+#pragma unroll
+        for (int j = 0; j < kSumRound; ++j) a[j] = Hu[9LL * i[j] + c];
+#pragma unroll
+        for (int j = 0; j < kSumRound; ++j) s += a[j];
     }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) A[(long long)c * nnzA + t] = s[c];
+    for (; q < qe; ++q) s += Hu[9LL * src[q] + c];
+    A[static_cast<long long>(c) * nnzA + t] = s;
 }
 
 __global__ void __launch_bounds__(256) k_coarse_sum_next(int nnzA, int nnzPrev, const int* __restrict__ ptr,
                                                           const int* __restrict__ src, const double* __restrict__ Ap,
                                                           double* __restrict__ A) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= nnzA) return;
-    double s[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int q = ptr[t]; q < ptr[t + 1]; ++q) {
-        const int k = src[q];
+    const long long gt = static_cast<long long>(blockIdx.x) * 256 + threadIdx.x;
+    if (gt >= 9LL * nnzA) return;
+    const int t = static_cast<int>(gt / 9), c = static_cast<int>(gt % 9);
+    const double* Apc = Ap + static_cast<long long>(c) * nnzPrev;
+    const int qe = ptr[t + 1];
+    int q = ptr[t];
+    double s = 0.0;
+    for (; q + kSumRound <= qe; q += kSumRound) {
+        int i[kSumRound];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) s[c] += Ap[(long long)c * nnzPrev + k];
+        for (int j = 0; j < kSumRound; ++j) i[j] = src[q + j];
+        double a[kSumRound];
+#pragma unroll
+        for (int j = 0; j < kSumRound; ++j) a[j] = Apc[i[j]];
+#pragma unroll
+        for (int j = 0; j < kSumRound; ++j) s += a[j];
     }
-#pragma unroll
-    for (int c = 0; c < 9; ++c) A[(long long)c * nnzA + t] = s[c];
+    for (; q < qe; ++q) s += Apc[src[q]];
+    A[static_cast<long long>(c) * nnzA + t] = s;
 }
 
 // ------------------------------------------------------- domain inversion
@@ -644,7 +665,7 @@ void launch_invert_t(const BuildView& b, const double* Hu, bool want32, int tota
 
 hipError_t launch_coarse_sums(const BuildView& b, const double* Hu, hipStream_t s) {
     for (int l = 1; l < b.L; ++l) {
-        const int g = ceil_div(b.nnzA[l], 256);
+        const int g = ceil_div(9LL * b.nnzA[l], 256);  // nine threads per coarse block
         if (g == 0) continue;
         if (l == 1)
             launch_kernel(k_coarse_sum_first, dim3(g), dim3(256), 0, s, b.nnzA[1], b.red_ptr[1], b.red_src[1], Hu,
