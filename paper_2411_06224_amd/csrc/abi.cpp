@@ -23,7 +23,7 @@ struct Layout {
     size_t total = 0;
     size_t remap, map, perm_src, perm_full, rp0, ci0, lead1, anc, g_u1, srp, sci, srow, tptr, tidx;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
-    size_t ganc, gpos, gmask, cp_ptr[kMaxLv], lmask;
+    size_t ganc, gpos, gmask, cp_ptr[kMaxLv], lmask, gorder;
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
     size_t b, x, r, z, p0, p1, q, r1, y[kMaxLv], cpart, P_sigma, P_rr, P_bb, P_rho0, P_rho1, st, flag;
     size_t inverse_bytes = 0;
@@ -146,6 +146,7 @@ void make_layout(mas_handle* h) {
     Y.lmask = Y.take(sizeof(uint64_t) * P.NS);
     Y.anc = Y.take(I * P.anc.size());
     Y.g_u1 = Y.take(I * P.g_u1.size());
+    Y.gorder = Y.take(I * P.gorder.size());
     const size_t gtab = P.L > 2 ? static_cast<size_t>(P.G) * (P.L - 2) * P.W1 : 0;  // [G][L-2][W1]
     Y.ganc = Y.take(I * gtab);
     Y.gpos = Y.take(I * gtab);
@@ -232,6 +233,7 @@ SolverView view(const mas_handle* h) {
         if (l >= 1) v.y[l] = at<double>(h, Y.y[l]);
     }
     v.g_u1 = at<int>(h, Y.g_u1);
+    v.gorder = P.gorder.empty() ? nullptr : at<int>(h, Y.gorder);
     v.ganc = at<int>(h, Y.ganc);
     v.gpos = at<int>(h, Y.gpos);
     v.gmask = at<uint64_t>(h, Y.gmask);
@@ -318,6 +320,7 @@ int upload_plan(mas_handle* h, hipStream_t s) {
                            s));
     HIP_TRY(put(Y.anc, P.anc));
     HIP_TRY(put(Y.g_u1, P.g_u1));
+    if (!P.gorder.empty()) HIP_TRY(put(Y.gorder, P.gorder));
     for (int l = 0; l < P.L; ++l) {
         if (l >= 1) {
             HIP_TRY(put(Y.red_ptr[l], P.red_ptr[l]));

@@ -39,6 +39,7 @@ struct SolverView {
                     // H32 (mixed) always holds the full storage (nnzb blocks)
     int nsb;        // blocks of the stored slot-ordered H (H64 / H32 planes)
     int maxT;       // most transposed entries of one group (symmetric storage)
+    const int* gorder;  // [G] SpMV group of each workgroup, or null: xcd_group
     int units[kMaxLv];
     int ndom[kMaxLv];
     // plans

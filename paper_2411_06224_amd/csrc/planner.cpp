@@ -261,6 +261,51 @@ void symmetric_storage(Plan& P) {
     P.sym = P.RG <= 256 && P.maxT <= kMaxTransposed;
 }
 
+// Workgroup order of the SpMV.  The group kernels give each XCD a
+// contiguous range of groups, dispatched in order.  Groups with far more
+// stored blocks than the mean (rows coupled to many distant columns, such as
+// the rows of bodies attached to a sheet) tend to sit together at one end of
+// the numbering, so one XCD gets all of them and starts them last.  When a
+// group holds more than 1.5x the mean, the heavy groups are dealt
+// round-robin over the XCDs, heaviest first, at the head of each XCD's
+// order, and each XCD is then filled with a contiguous run of the other
+// groups (keeping neighbouring groups, which share halo entries, on one
+// XCD).  Otherwise gorder stays empty.
+void spmv_order(Plan& P) {
+    P.gorder.clear();
+    const int G = P.G, NS = P.NS, RG = P.RG;
+    if (G <= 0) return;
+    const std::vector<int>& rp = P.sym ? P.srp : P.rp0;
+    std::vector<long long> cnt(G);
+    double mean = 0.0;
+    for (int g = 0; g < G; ++g) {
+        const int r0 = g * RG, r1 = std::min(r0 + RG, NS);
+        cnt[g] = rp[r1] - rp[r0];
+        mean += static_cast<double>(cnt[g]);
+    }
+    mean /= G;
+    std::vector<int> heavy, light;
+    for (int g = 0; g < G; ++g) (static_cast<double>(cnt[g]) > 1.5 * mean ? heavy : light).push_back(g);
+    if (heavy.empty()) return;
+    std::stable_sort(heavy.begin(), heavy.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+    const int q = G / kXcdCount, rem = G % kXcdCount;
+    std::array<std::vector<int>, kXcdCount> lists;
+    auto cap = [&](int x) { return static_cast<size_t>(q + (x < rem ? 1 : 0)); };
+    int x = 0;
+    for (const int g : heavy) {
+        while (lists[x].size() == cap(x)) x = (x + 1) % kXcdCount;
+        lists[x].push_back(g);
+        x = (x + 1) % kXcdCount;
+    }
+    size_t li = 0;
+    for (x = 0; x < kXcdCount; ++x)
+        while (lists[x].size() < cap(x)) lists[x].push_back(light[li++]);
+    // workgroup b = i kXcdCount + x runs the i-th group of XCD x's list
+    P.gorder.assign(G, -1);
+    for (x = 0; x < kXcdCount; ++x)
+        for (size_t i = 0; i < lists[x].size(); ++i) P.gorder[i * kXcdCount + x] = lists[x][i];
+}
+
 }  // namespace
 
 std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* g_ptr,
@@ -517,6 +562,7 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
     }
 
     symmetric_storage(P);
+    spmv_order(P);
 
     // ---- per-node units for reports
     P.sn.assign(static_cast<size_t>(P.L) * V, -1);

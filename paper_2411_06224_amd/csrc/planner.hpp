@@ -13,6 +13,9 @@ constexpr int kMaxLevels = 16;
 // The symmetric storage keeps a group's transposed-entry list in LDS; groups
 // with more entries than this use the full storage.
 constexpr int kMaxTransposed = 4096;
+// The group kernels deal workgroup b to XCD b % kXcdCount, each XCD taking a
+// contiguous range of groups (xcd_group on the device).
+constexpr int kXcdCount = 8;
 
 struct Plan {
     int V = 0;      // nodes (block rows of H)
@@ -90,6 +93,10 @@ struct Plan {
     std::vector<int> srp, sci, sperm, tptr, tidx;
     std::vector<uint8_t> srow;
     int maxT = 0;
+
+    // SpMV group of each workgroup when the groups' stored blocks are
+    // uneven (empty: the contiguous per-XCD mapping of the group kernels)
+    std::vector<int> gorder;
 
     std::vector<int> sn;  // [L * V] unit of each node per level (level 0 = slot), for reports
 };

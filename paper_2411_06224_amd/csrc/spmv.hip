@@ -107,6 +107,13 @@ __device__ __forceinline__ ChunkCols chunk_cols(const int* __restrict__ ci, int 
     return c;
 }
 
+// The group a workgroup of the matrix-streaming kernels takes: the
+// planner's order when the groups' stored blocks are uneven, else the
+// contiguous per-XCD mapping of every group kernel.
+__device__ __forceinline__ int spmv_group(const SolverView& v) {
+    return v.gorder ? v.gorder[blockIdx.x] : xcd_group(blockIdx.x, v.G);
+}
+
 // Row sums of rows [r0, r1) of H x.  Owner o = 3 (row - r0) + c is thread
 // o (acc[0]) or o - 256 (acc[1]); 3 (r1 - r0) <= 512.  prod: 3 * kPlane LDS.
 // kLds: x of the columns r0 .. r1 - 1 is read from xs (LDS), the others
@@ -314,7 +321,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     __shared__ double buf[256];
     __shared__ double xs[384];
     const int t = threadIdx.x;
-    const int g = xcd_group(blockIdx.x, v.G);
+    const int g = spmv_group(v);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     const int nown = 3 * (r1 - r0);
     // every independent load before the first wait: the rho partials first
@@ -378,7 +385,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     __shared__ double buf[256];
     extern __shared__ double dyn[];  // xs[3 RG] doubles + tl[maxT] ints
     const int t = threadIdx.x;
-    const int g = xcd_group(blockIdx.x, v.G);
+    const int g = spmv_group(v);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     const int nown = 3 * (r1 - r0);
     double* xs = dyn;
@@ -453,7 +460,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
     __shared__ double scratch[kThreads / 64];
     extern __shared__ double dyn[];  // rs[3*RG] + restriction scratch (+ xs[3*RG] + tl[maxT] ints)
     if (kMode == kResidReplace && v.st->done) return;
-    const int g = xcd_group(blockIdx.x, v.G);
+    const int g = spmv_group(v);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     double acc[2];
     const RestrictLoads pl = restrict_load(v, g);
