@@ -17,6 +17,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, NOT_CONVERGED, INVALID, NOT_SPD = 0, 1, -1, -2
+DOT_SEQUENTIAL, DOT_COMPENSATED = 0, 1
 MAX_LEVELS = 16
 
 
@@ -74,8 +75,12 @@ def lib():
         L.orc_mas_get_domain_matrix.argtypes = [_vp, _i, _i, _pd]
         L.orc_mas_get_inverse.argtypes = [_vp, _i, _i, _pd]
         L.orc_mas_apply.argtypes = [_vp, _pd, _pd]
+        L.orc_mas_perturb.argtypes = [_vp, _d, ctypes.c_ulonglong]
         L.orc_spmv.argtypes = [_i, _pi, _pi, _pd, _pd, _pd]
         L.orc_pcg.argtypes = [_i, _pi, _pi, _pd, _vp, _pd, _pd, _d, _i, _pi, _pd, _pd]
+        L.orc_pcg_dots.argtypes = [_i, _pi, _pi, _pd, _vp, _pd, _pd, _d, _i, _i, _pi, _pd, _pd]
+        L.orc_dot.argtypes = [_i, _pd, _pd, _i]
+        L.orc_dot.restype = _d
         L.orc_adjoint_scatter.argtypes = [_i, _pi, _pi, _pd, _pd, _pd]
         L.orc_assemble.argtypes = [_i, ctypes.c_long, _pi, _pi, _pd, _pi, _pi, _pd]
         L.orc_assemble.restype = ctypes.c_long
@@ -125,6 +130,16 @@ def spmv(row_ptr, col_idx, val, x):
     y = np.empty(3 * n)
     lib().orc_spmv(n, rpp, cip, vp, xp, y.ctypes.data_as(_pd))
     return y
+
+
+def dot(a, b, mode=DOT_SEQUENTIAL):
+    """a . b as the oracle's PCG forms it: ``DOT_SEQUENTIAL`` (ascending, working
+    precision) or ``DOT_COMPENSATED`` (Dot2 of Ogita, Rump and Oishi)."""
+    a, ap = _cd(a)
+    b, bp = _cd(b)
+    if a.size != b.size:
+        raise ValueError("dot of vectors of different lengths")
+    return lib().orc_dot(int(a.size), ap, bp, int(mode))
 
 
 def adjoint_scatter(row_ptr, col_idx, lam, x):
@@ -235,18 +250,25 @@ class MAS:
         lib().orc_mas_get_inverse(self._h, l, d, out.ctypes.data_as(_pd))
         return out
 
+    def perturb(self, eps, seed):
+        """Scales every inverse entry by (1 + eps u), u ~ U[-1, 1) from
+        SplitMix64 at (seed, entry index), keeping each inverse symmetric.
+        Test infrastructure for the iteration-count contract only."""
+        lib().orc_mas_perturb(self._h, float(eps), int(seed))
+
     def apply(self, r):
         r, rp_ = _cd(r)
         z = np.empty(3 * self.V)
         lib().orc_mas_apply(self._h, rp_, z.ctypes.data_as(_pd))
         return z
 
-    def pcg(self, b, tol=1e-8, max_iter=10000):
-        """Returns ``(x, status, iterations, rel_residual, true_rel_residual)``."""
+    def pcg(self, b, tol=1e-8, max_iter=10000, dots=DOT_SEQUENTIAL):
+        """Returns ``(x, status, iterations, rel_residual, true_rel_residual)``;
+        ``dots`` selects how the dot products are summed (see :func:`dot`)."""
         b, bp = _cd(b)
         x = np.empty(3 * self.V)
         it, rr, tr = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
-        s = lib().orc_pcg(
+        s = lib().orc_pcg_dots(
             self.V,
             self._rp.ctypes.data_as(_pi),
             self._ci.ctypes.data_as(_pi),
@@ -256,6 +278,7 @@ class MAS:
             x.ctypes.data_as(_pd),
             float(tol),
             int(max_iter),
+            int(dots),
             ctypes.byref(it),
             ctypes.byref(rr),
             ctypes.byref(tr),

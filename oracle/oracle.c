@@ -486,6 +486,39 @@ void orc_mas_get_inverse(const orc_mas* P, int l, int d, double* Inv) {
     memcpy(Inv, P->Inv[l] + (size_t)d * n2, n2 * sizeof(double));
 }
 
+/* Rounding-level perturbation of the preconditioner, for deriving how far two
+ * correct FP64 implementations of the same MAS operator may drift apart in
+ * their PCG iteration counts (test infrastructure, no part of the method).
+ * Every stored inverse entry (p <= q) of every level and domain is scaled by
+ * (1 + eps * u) with u uniform in [-1, 1), and mirrored, so each inverse
+ * stays exactly symmetric.  u comes from SplitMix64 (Steele, Lea and Flood,
+ * "Fast splittable pseudorandom number generators", OOPSLA 2014) evaluated
+ * at counter (seed, running entry index): state = seed + (index + 1) * gamma
+ * with gamma = 0x9e3779b97f4a7c15, then the published 64-bit finaliser. */
+static unsigned long long splitmix64_at(unsigned long long seed, unsigned long long index) {
+    unsigned long long z = seed + (index + 1ULL) * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+void orc_mas_perturb(orc_mas* P, double eps, unsigned long long seed) {
+    int n3 = 3 * P->N;
+    unsigned long long idx = 0;
+    for (int l = 0; l < P->L; ++l)
+        for (int d = 0; d < P->ndom[l]; ++d) {
+            double* A = P->Inv[l] + (size_t)d * n3 * n3;
+            for (int p = 0; p < n3; ++p)
+                for (int q = p; q < n3; ++q) {
+                    /* top 53 bits -> [0, 1) -> [-1, 1) */
+                    double u = (double)(splitmix64_at(seed, idx++) >> 11) * (1.0 / 9007199254740992.0);
+                    double v = A[p * n3 + q] * (1.0 + eps * (2.0 * u - 1.0));
+                    A[p * n3 + q] = v;
+                    A[q * n3 + p] = v;
+                }
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* MAS apply (Supp. Eq. 4-6)                                                */
 /* ------------------------------------------------------------------------ */
@@ -537,14 +570,43 @@ void orc_spmv(int n, const int* rp, const int* ci, const double* val, const doub
     }
 }
 
-static double dot(int m, const double* a, const double* b) {
+static double dot_seq(int m, const double* a, const double* b) {
     double s = 0.0;
     for (int i = 0; i < m; ++i) s += a[i] * b[i];
     return s;
 }
 
+/* Compensated dot product, algorithm Dot2 of Ogita, Rump and Oishi
+ * ("Accurate sum and dot product", SIAM J. Sci. Comput. 26(6), 2005): the
+ * result is as accurate as if the sum were accumulated in twice the working
+ * precision and rounded once.  Error-free transformations: TwoProduct with an
+ * explicit fused multiply-add, TwoSum by Knuth's branch-free form. */
+static double dot_comp(int m, const double* a, const double* b) {
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < m; ++i) {
+        double p = a[i] * b[i];
+        double ep = fma(a[i], b[i], -p);
+        double t = s + p;
+        double z = t - s;
+        double es = (s - (t - z)) + (p - z);
+        s = t;
+        c += es + ep;
+    }
+    return s + c;
+}
+
+double orc_dot(int m, const double* a, const double* b, int dot_mode) {
+    return dot_mode == ORC_DOT_COMPENSATED ? dot_comp(m, a, b) : dot_seq(m, a, b);
+}
+
 int orc_pcg(int n, const int* rp, const int* ci, const double* val, const orc_mas* P, const double* b, double* x,
             double tol, int max_iter, int* iters, double* relres, double* true_relres) {
+    return orc_pcg_dots(n, rp, ci, val, P, b, x, tol, max_iter, ORC_DOT_SEQUENTIAL, iters, relres, true_relres);
+}
+
+int orc_pcg_dots(int n, const int* rp, const int* ci, const double* val, const orc_mas* P, const double* b,
+                 double* x, double tol, int max_iter, int dot_mode, int* iters, double* relres, double* true_relres) {
+#define dot(m_, a_, b_) orc_dot((m_), (a_), (b_), dot_mode)
     int m = 3 * n;
     for (int i = 0; i < m; ++i) x[i] = 0.0;
     *iters = 0;
@@ -595,6 +657,7 @@ int orc_pcg(int n, const int* rp, const int* ci, const double* val, const orc_ma
     free(p);
     free(q);
     return status;
+#undef dot
 }
 
 /* dL/dH_ij = -lambda_i x_j^T on every stored block (from dx = -H^-1 dH x). */

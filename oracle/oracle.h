@@ -73,10 +73,25 @@ void orc_mas_get_sn(const orc_mas* P, int l, int* sn); /* sn[V]: unit of each no
 void orc_mas_get_domain_matrix(const orc_mas* P, int l, int d, double* K);
 void orc_mas_get_inverse(const orc_mas* P, int l, int d, double* Inv);
 
+/* Test infrastructure: scales every inverse entry (p <= q, mirrored) by
+ * (1 + eps u), u uniform in [-1, 1) from SplitMix64 at (seed, entry index).
+ * Used only to measure how PCG iteration counts spread under rounding-level
+ * changes of the preconditioner; eps = 0 leaves the inverses unchanged. */
+void orc_mas_perturb(orc_mas* P, double eps, unsigned long long seed);
 void orc_mas_apply(const orc_mas* P, const double* r, double* z);
 void orc_spmv(int n, const int* rp, const int* ci, const double* val, const double* x, double* y);
 int orc_pcg(int n, const int* rp, const int* ci, const double* val, const orc_mas* P, const double* b,
             double* x, double tol, int max_iter, int* iters, double* relres, double* true_relres);
+/* Dot products of orc_pcg_dots: ORC_DOT_SEQUENTIAL sums the products in
+ * ascending order in working precision (what orc_pcg does);
+ * ORC_DOT_COMPENSATED uses the compensated algorithm Dot2 (Ogita, Rump and
+ * Oishi 2005), as accurate as a sum in twice the working precision.  Both are
+ * evaluations of the same definition; PCG iteration counts depend on which. */
+#define ORC_DOT_SEQUENTIAL 0
+#define ORC_DOT_COMPENSATED 1
+double orc_dot(int m, const double* a, const double* b, int dot_mode);
+int orc_pcg_dots(int n, const int* rp, const int* ci, const double* val, const orc_mas* P, const double* b,
+                 double* x, double tol, int max_iter, int dot_mode, int* iters, double* relres, double* true_relres);
 void orc_adjoint_scatter(int n, const int* rp, const int* ci, const double* lambda, const double* x,
                          double* dLdH);
 

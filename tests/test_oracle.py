@@ -481,3 +481,111 @@ def test_assemble_reproduces_generated_cube():
     rp, ci, val = oracle.assemble(s.n, rows, cols, blocks)
     assert np.array_equal(rp, s.row_ptr) and np.array_equal(ci, s.col_idx)
     assert np.allclose(val, s.val, rtol=1e-12, atol=1e-12 * np.abs(s.val).max())
+
+
+# ------------------------------------------ dot modes and perturbation ---
+# Used only to derive the iteration-count contract (tests/golden/
+# count_ensemble_cube48.json); pinned here against exact arithmetic.
+
+
+def _exact_dot(a, b):
+    from fractions import Fraction
+
+    return sum((Fraction(float(x)) * Fraction(float(y)) for x, y in zip(a, b)), Fraction(0))
+
+
+def test_compensated_dot_recovers_cancelled_terms():
+    # 1e16 + 1 - 1e16: the plain sum loses the 1, the compensated one keeps it
+    a = np.array([1e16, 1.0, -1e16])
+    b = np.ones(3)
+    assert oracle.dot(a, b, oracle.DOT_SEQUENTIAL) == 0.0
+    assert oracle.dot(a, b, oracle.DOT_COMPENSATED) == 1.0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_compensated_dot_error_bound(seed):
+    # Dot2 (Ogita, Rump, Oishi 2005, Prop. 5.5 / Thm 5.3): |res - a.b| <= u |a.b| + gamma_n^2 sum |a_i b_i|
+    rng = np.random.default_rng(seed)
+    n = 2000
+    a = rng.standard_normal(n) * np.exp(rng.uniform(-30, 30, n))
+    b = rng.standard_normal(n) * np.exp(rng.uniform(-30, 30, n))
+    # ill-conditioned: append the negated sum of a few large products
+    a = np.concatenate([a, -a[:50]])
+    b = np.concatenate([b, b[:50]])
+    exact = _exact_dot(a, b)
+    u = 2.0 ** -53
+    n2 = a.size
+    gamma = n2 * u / (1 - n2 * u)
+    absum = float(np.sum(np.abs(a * b)))
+    comp = oracle.dot(a, b, oracle.DOT_COMPENSATED)
+    seq = oracle.dot(a, b, oracle.DOT_SEQUENTIAL)
+    err_c = abs(float(exact - type(exact)(comp)))
+    assert err_c <= u * abs(float(exact)) + gamma ** 2 * absum
+    # the plain sum meets only the classical bound gamma_n sum |a_i b_i|
+    assert abs(float(exact - type(exact)(seq))) <= gamma * absum
+
+
+def test_pcg_dot_modes():
+    s = small_cube()
+    P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=16, max_levels=2, gptr=s.gptr, gadj=s.gadj)
+    x0, st0, it0, *_ = P.pcg(s.b, tol=1e-10)
+    lib = oracle.lib()
+    # the default PCG is the sequential mode, bit for bit
+    import ctypes
+
+    xr = np.empty(3 * s.n)
+    it, rr, tr = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    rp = np.ascontiguousarray(s.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(s.col_idx, dtype=np.int32)
+    vv = np.ascontiguousarray(s.val, dtype=np.float64).reshape(-1)
+    bb = np.ascontiguousarray(s.b, dtype=np.float64)
+    st = lib.orc_pcg(s.n, rp.ctypes.data_as(oracle._pi), ci.ctypes.data_as(oracle._pi),
+                     vv.ctypes.data_as(oracle._pd), P._h, bb.ctypes.data_as(oracle._pd),
+                     xr.ctypes.data_as(oracle._pd), 1e-10, 10000, ctypes.byref(it), ctypes.byref(rr), ctypes.byref(tr))
+    assert st == st0 == oracle.OK and it.value == it0
+    assert np.array_equal(xr.view(np.uint64), x0.view(np.uint64))
+    # compensated dots: same solution up to the tolerance, Cholesky as the judge
+    x1, st1, it1, *_ = P.pcg(s.b, tol=1e-10, dots=oracle.DOT_COMPENSATED)
+    H = sparse_dense(s)
+    xs = sla.cho_solve(sla.cho_factor(H), s.b)
+    assert st1 == oracle.OK and abs(it1 - it0) <= 2
+    assert np.linalg.norm(x1 - xs) <= 1e-7 * np.linalg.norm(xs)
+
+
+def sparse_dense(s):
+    import scipy.sparse as sp
+
+    return sp.bsr_matrix((s.val.reshape(-1, 3, 3), s.col_idx, s.row_ptr), shape=(3 * s.n, 3 * s.n)).toarray()
+
+
+def test_perturbation_of_inverses():
+    s = cube(4, 1e6, 0.45, seed=3, n_contacts=10)
+    args = (s.row_ptr, s.col_idx, s.val)
+    kw = dict(N=8, gptr=s.gptr, gadj=s.gadj)
+    P0 = oracle.MAS(*args, **kw)
+    L = P0.levels
+    ref = [[P0.inverse(l, d) for d in range(P0.domains(l))] for l in range(L)]
+    P0.perturb(0.0, 7)  # eps = 0 changes nothing
+    for l in range(L):
+        for d in range(P0.domains(l)):
+            assert np.array_equal(P0.inverse(l, d), ref[l][d])
+    eps = 1e-6
+    Pa, Pb, Pc = oracle.MAS(*args, **kw), oracle.MAS(*args, **kw), oracle.MAS(*args, **kw)
+    Pa.perturb(eps, 7)
+    Pb.perturb(eps, 7)
+    Pc.perturb(eps, 8)
+    ratios = []
+    for l in range(L):
+        for d in range(P0.domains(l)):
+            A, B, C, R = Pa.inverse(l, d), Pb.inverse(l, d), Pc.inverse(l, d), ref[l][d]
+            assert np.array_equal(A, A.T)  # stays exactly symmetric
+            assert np.array_equal(A, B)  # same seed, same perturbation
+            nz = R != 0
+            assert np.array_equal(A != 0, nz)  # zero lanes stay zero
+            q = (A[nz] - R[nz]) / R[nz] / eps
+            ratios.append(q)
+            assert not np.array_equal(A[nz], C[nz])  # another seed, another perturbation
+    q = np.concatenate(ratios)
+    # u ~ U[-1, 1): bounded by one, centred, spread as a uniform variable (variance 1/3)
+    assert np.all(np.abs(q) <= 1.0 + 1e-6)
+    assert abs(q.mean()) < 0.05 and abs(q.var() - 1.0 / 3.0) < 0.05
