@@ -261,6 +261,23 @@ int mas_get_info(const mas_handle* h, mas_info* out);
  * NULL.  Errors: MAS_NOT_READY. */
 int mas_get_ordering(const mas_handle* h, int32_t* map, int32_t* remap, int32_t* sn);
 
+/* Host copy of the domain inverses Inv_{l,d} = (S_d C_l H C_l^T S_d^T)^-1 of
+ * level l as the last mas_build left them (the per-domain inverses of
+ * Supp. Eq. 6; inverted over the occupied lanes, Sec. 4.2), for checking them
+ * against a reference.
+ *   level: 0 <= level < levels.
+ *   precision: MAS_PRECISION_F64 for the FP64 inverses, MAS_PRECISION_MIXED
+ *              for the FP32 copy of a mixed-precision handle (widened).
+ *   out: host, ndom[level] * (3N)^2 doubles; domain d at d (3N)^2, entry
+ *        (i, j) at d (3N)^2 + j 3N + i (column-major; the inverses are
+ *        symmetric), DOF 3 a + c of lane a.  Unoccupied lanes are zero rows
+ *        and columns.  Inverses kept symmetric-packed on the device are
+ *        expanded.
+ * Synchronises the stream.  Errors: MAS_NOT_READY (no successful
+ * mas_build), MAS_INVALID_ARG (level out of range, FP32 copy asked of an FP64
+ * handle), MAS_HIP_ERROR. */
+int mas_get_inverses(const mas_handle* h, int32_t level, int32_t precision, double* out, void* stream);
+
 /* Device time in milliseconds of the phases of the last mas_build and
  * pcg_solve / pcg_adjoint call on this handle, measured with HIP events on
  * the call's stream: [0] coarse sums and [1] batched inversion (mas_build),

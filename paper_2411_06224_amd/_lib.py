@@ -40,6 +40,7 @@ SYMBOLS = (
     "mas_hierarchy_device",
     "mas_get_info",
     "mas_get_ordering",
+    "mas_get_inverses",
     "mas_get_timings",
     "mas_set_kernel_timing",
     "mas_get_kernel_timing",
@@ -156,6 +157,8 @@ def load():
     L.mas_get_info.restype = ctypes.c_int
     L.mas_get_ordering.argtypes = [vp, vp, vp, vp]
     L.mas_get_ordering.restype = ctypes.c_int
+    L.mas_get_inverses.argtypes = [vp, i32, i32, vp, vp]
+    L.mas_get_inverses.restype = ctypes.c_int
     L.mas_get_timings.argtypes = [vp, P(ctypes.c_double)]
     L.mas_get_timings.restype = ctypes.c_int
     L.mas_set_kernel_timing.argtypes = [vp, ctypes.c_int]

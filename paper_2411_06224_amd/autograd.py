@@ -5,6 +5,10 @@ preconditioner (H is symmetric, so the preconditioner built for the forward
 system also serves the adjoint one) and returns dL/db = lambda and
 dL/dH_ij = -lambda_i x_j^T on every stored block (from dx = -H^-1 (dH) x).
 Both the solve and the scatter run in the library's HIP kernels.
+
+Neither solve may stop at max_iter: a forward solve that does not reach tol
+raises MasError (x would not be H^-1 b), and so does an adjoint solve that
+does not (lambda, dL/db and dL/dH would not be the gradient).
 """
 
 import torch
@@ -18,7 +22,7 @@ class MasPcgSolve(torch.autograd.Function):
         H = BlockMatrix(row_ptr, col_idx, val.detach())
         if rebuild:
             solver.build(H)
-        x, res = solver.solve(H, b.detach(), tol=tol, max_iter=max_iter)
+        x, res = solver.solve(H, b.detach(), tol=tol, max_iter=max_iter, allow_not_converged=False)
         ctx.solver = solver
         ctx.tol = tol
         ctx.max_iter = max_iter
@@ -38,6 +42,7 @@ class MasPcgSolve(torch.autograd.Function):
             want_dH=ctx.needs_input_grad[0],
             tol=ctx.tol,
             max_iter=ctx.max_iter,
+            allow_not_converged=False,
         )
         ctx.adjoint_result = res
         dval = dH.view_as(val) if dH is not None else None

@@ -782,6 +782,47 @@ int mas_get_ordering(const mas_handle* h, int32_t* map, int32_t* remap, int32_t*
     return MAS_OK;
 }
 
+int mas_get_inverses(const mas_handle* h, int32_t level, int32_t precision, double* out, void* stream) {
+    if (!h || !out) return MAS_INVALID_ARG;
+    if (!h->analyzed || !h->built) return MAS_NOT_READY;
+    const Plan& P = h->plan;
+    if (level < 0 || level >= P.L) return MAS_INVALID_ARG;
+    const bool want32 = precision == MAS_PRECISION_MIXED;
+    if (!want32 && precision != MAS_PRECISION_F64) return MAS_INVALID_ARG;
+    if (want32 && h->opts.precision != MAS_PRECISION_MIXED) return MAS_INVALID_ARG;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = 3 * P.N;
+    const size_t nd = static_cast<size_t>(P.ndom[level]), full = nd * n * n;
+    if (want32) {
+        std::vector<float> tmp(full);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), h->ws + h->lay.inv32[level], sizeof(float) * full, hipMemcpyDeviceToHost,
+                               s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (size_t e = 0; e < full; ++e) out[e] = static_cast<double>(tmp[e]);
+        return MAS_OK;
+    }
+    if (level == 0 && P.N == 16) {  // symmetric-packed: lower triangle column by column
+        std::vector<double> tmp(nd * kPacked);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), h->ws + h->lay.inv64[0], sizeof(double) * tmp.size(),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (size_t d = 0; d < nd; ++d) {
+            const double* src = tmp.data() + d * kPacked;
+            double* dst = out + d * n * n;
+            for (int j = 0; j < n; ++j)
+                for (int i = j; i < n; ++i) {
+                    const double val = src[packed_col(j) + i - j];
+                    dst[static_cast<size_t>(j) * n + i] = val;
+                    dst[static_cast<size_t>(i) * n + j] = val;
+                }
+        }
+        return MAS_OK;
+    }
+    HIP_TRY(hipMemcpyAsync(out, h->ws + h->lay.inv64[level], sizeof(double) * full, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAS_OK;
+}
+
 int mas_get_timings(const mas_handle* h, double* ms4) {
     if (!h || !ms4) return MAS_INVALID_ARG;
     for (int k = 0; k < 4; ++k) ms4[k] = h->timings[k];

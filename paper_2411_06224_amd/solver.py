@@ -225,6 +225,19 @@ class MasPcg:
         )
         return mp, rm, sn
 
+    def inverses(self, level, precision=None):
+        """Host copy of level ``level``'s domain inverses after :meth:`build`:
+        array [ndom, 3N, 3N] (zero rows/columns on unoccupied lanes).
+        ``precision="mixed"`` reads the FP32 copy of a mixed handle."""
+        inf = self.info()
+        n = 3 * inf["domain_size"]
+        out = np.empty((inf["domains"][level], n, n), np.float64)
+        prec = {"f64": MAS_PRECISION_F64, "mixed": MAS_PRECISION_MIXED}[precision or "f64"]
+        check("mas_get_inverses",
+              self._L.mas_get_inverses(self._h, int(level), prec, out.ctypes.data_as(ctypes.c_void_p), _stream()))
+        # stored column-major per domain: transpose to row-major (a no-op for exact symmetry)
+        return out.transpose(0, 2, 1).copy()
+
     def hierarchy_device(self, device=None):
         """Supernode hierarchy rebuilt on the device from the analysed pattern.
 
@@ -325,8 +338,11 @@ class MasPcg:
         check("pcg_solve", rc, (MAS_OK, MAS_NOT_CONVERGED) if allow_not_converged else (MAS_OK,))
         return x, self._result(res)
 
-    def adjoint(self, H, x, dLdx, dLdH_dtype=torch.float64, want_dH=True, tol=1e-4, max_iter=10000, replace_every=50, check_every=8):
-        """Returns ``(lambda = dL/db, dL/dH blocks or None, result)``."""
+    def adjoint(self, H, x, dLdx, dLdH_dtype=torch.float64, want_dH=True, tol=1e-4, max_iter=10000, replace_every=50, check_every=8,
+                allow_not_converged=True):
+        """Returns ``(lambda = dL/db, dL/dH blocks or None, result)``; raises
+        MasError on failure (also on MAS_NOT_CONVERGED when
+        ``allow_not_converged`` is False)."""
         _need_cuda(x, "x", torch.float64)
         _need_cuda(dLdx, "dLdx", torch.float64)
         lam = torch.empty_like(dLdx)
@@ -350,5 +366,5 @@ class MasPcg:
             ctypes.byref(res),
             _stream(),
         )
-        check("pcg_adjoint", rc, (MAS_OK, MAS_NOT_CONVERGED))
+        check("pcg_adjoint", rc, (MAS_OK, MAS_NOT_CONVERGED) if allow_not_converged else (MAS_OK,))
         return lam, dH, self._result(res)

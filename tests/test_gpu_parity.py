@@ -5,7 +5,8 @@ Tolerances:
   MAS apply (FP64)        ||z - z_ref|| <= 1e-10 ||z_ref||
   PCG, fixed iterations   ||x_k - x_k,ref|| <= 1e-10 ||x_k,ref||
   PCG, converged          both meet tol on the true residual; the iteration count within
-                          +-2 of the oracle's counts for b perturbed at the rounding level
+                          2 of the range the oracle spans under rounding-level changes
+                          (count_contract.py); x within twice the oracle's own spread
   tight solve             ||x - x_ref|| <= 1e-10 ||x_ref|| at tol 1e-13
   mixed precision         true FP64 residual <= tol; error vs the FP64 oracle printed
   gradients               vs dense FP64 gradient <= 1e-8 relative
@@ -19,6 +20,7 @@ import pytest
 import oracle
 import synth
 from conftest import cube, large_cube, small_cube
+from count_contract import oracle_ensemble
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -64,16 +66,10 @@ def _oracle(s, N=16, max_levels=0, graph=True):
     return oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels)
 
 
-def _oracle_count_range(P, b, tol, n=8):
-    """Oracle iteration counts for b and for b perturbed at the rounding level
-    (relative 1e-15).  On an ill-conditioned system the arithmetic fixes
-    PCG's iteration count only up to this spread (the contact cube at 1e-6
-    spans 226-230), so the GPU count is checked against it, +-2."""
-    rng = np.random.default_rng(123)
-    its = [P.pcg(b, tol=tol)[2]]
-    for _ in range(n - 1):
-        its.append(P.pcg(b * (1.0 + 1e-15 * rng.standard_normal(b.shape)), tol=tol)[2])
-    return min(its) - 2, max(its) + 2
+def _count_contract(s, tol, N=16, graph=True):
+    """(lo, hi, x_tol, x_ref) of count_contract.oracle_ensemble for system s."""
+    lo, hi, xt, x0, _ = oracle_ensemble(lambda: _oracle(s, N, graph=graph), s.b, tol)
+    return lo, hi, xt, x0
 
 
 def _absH_absx(s, x):
@@ -199,12 +195,40 @@ def test_pcg_converged(dev, name, N, tol):
     S.build(H)
     x, res = S.solve(H, _t(s.b, dev), tol=tol)
     assert res["status"] == 0 and st == 0
-    lo, hi = _oracle_count_range(P, s.b, tol)
+    lo, hi, xt, _ = _count_contract(s, tol, N)
     assert lo <= res["iterations"] <= hi, (res["iterations"], it, lo, hi)
     assert res["true_rel_residual"] <= tol * 1.01
     xv = x.cpu().numpy()
+    assert np.linalg.norm(xv - xr) <= xt * np.linalg.norm(xr), (np.linalg.norm(xv - xr) / np.linalg.norm(xr), xt)
     true = np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) / np.linalg.norm(s.b)
     assert true <= tol * 1.01
+
+
+@pytest.mark.parametrize("name,N,ml", [("cube8", 16, 2), ("cube8", 16, 0), ("contact6", 16, 0), ("rand300", 8, 0),
+                                        ("cube3_stiff", 4, 0), ("cube2", 5, 0)])
+def test_inverses(dev, name, N, ml):
+    """P3: every domain inverse of every level against the oracle's,
+    relative Frobenius <= 1e-10 (FP64); the FP32 copy of a mixed handle
+    within FP32 rounding of the FP64 one."""
+    _say("inverses", name, N, ml)
+    s = SYSTEMS[name]()
+    P = _oracle(s, N, ml)
+    H = _H(s, dev)
+    for prec in ("f64", "mixed"):
+        S = _solver(s, N, ml, precision=prec)
+        S.build(H)
+        assert S.info()["levels"] == P.levels
+        for l in range(P.levels):
+            G = S.inverses(l)
+            for d in range(G.shape[0]):
+                R = P.inverse(l, d)
+                e = np.linalg.norm(G[d] - R) / np.linalg.norm(R)
+                assert e <= 1e-10, (prec, l, d, e)
+            if prec == "mixed":  # the FP32 copy: each entry the FP64 one rounded (up to the
+                # kappa u asymmetry of the unsymmetrised inverse the FP32 copy is cast from)
+                G32 = S.inverses(l, "mixed")
+                assert np.all(np.abs(G32 - G) <= 2.0 ** -24 * np.abs(G) + 1e-10 * np.abs(G).max())
+        S.close()
 
 
 def test_pcg_small_cube_tight(dev):
@@ -362,9 +386,10 @@ def test_pcg_long_range_couplings(dev):
     assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
     xr, st, it, *_ = P.pcg(s.b, tol=1e-8)
     x, res = S.solve(H, _t(s.b, dev), tol=1e-8)
-    lo, hi = _oracle_count_range(P, s.b, 1e-8)
+    lo, hi, xt, _ = _count_contract(s, 1e-8)
     assert res["status"] == 0 and st == 0 and lo <= res["iterations"] <= hi
     xv = x.cpu().numpy()
+    assert np.linalg.norm(xv - xr) <= xt * np.linalg.norm(xr)
     assert np.linalg.norm(s.b - oracle.spmv(s.row_ptr, s.col_idx, s.val, xv)) <= 1.01e-8 * np.linalg.norm(s.b)
 
 
@@ -414,6 +439,30 @@ def test_adjoint_dense_gradient_small_cube(dev):
     G = val.grad.cpu().numpy()
     Gr = oracle.adjoint_scatter(s.row_ptr, s.col_idx, lam, xs)
     assert np.linalg.norm(G - Gr) <= 1e-8 * np.linalg.norm(Gr)
+
+
+def test_autograd_raises_when_a_solve_does_not_converge(dev):
+    """The differentiable solve refuses a forward (or adjoint) solve that stops
+    at max_iter: its x, dL/db and dL/dH would not be the gradient."""
+    from paper_2411_06224_amd import BlockMatrix, MasError, mas_pcg_solve
+
+    _say("autograd max_iter too low")
+    s = small_cube()
+    S = _solver(s, 16, 2)
+    H = _H(s, dev)
+    val = H.val.clone().requires_grad_(True)
+    b = _t(s.b, dev).requires_grad_(True)
+    with pytest.raises(MasError):
+        mas_pcg_solve(S, BlockMatrix(H.row_ptr, H.col_idx, val), b, tol=1e-12, max_iter=3)
+    # forward converges, adjoint may not: it raises as well
+    x = mas_pcg_solve(S, BlockMatrix(H.row_ptr, H.col_idx, val), b, tol=1e-8, max_iter=10000)
+    S2 = _solver(s, 16, 2)
+    S2.build(H)
+    with pytest.raises(MasError):
+        S2.adjoint(H, x.detach(), x.detach().clone(), tol=1e-12, max_iter=3, allow_not_converged=False)
+    loss = 0.5 * (x ** 2).sum()
+    loss.backward()  # the adjoint converges at the forward's max_iter
+    assert torch.isfinite(b.grad).all()
 
 
 def test_adjoint_matches_oracle_scatter_f32(dev):
