@@ -230,6 +230,28 @@ int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
                   int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/* Scratch bytes held by bcsr_assemble_noalloc on each device it runs on. */
+#define MAS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* bcsr_assemble for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation, arguments and results, with the scratch
+ * taken from a static device array of MAS_NOALLOC_SCRATCH_BYTES that each
+ * device the library runs on holds from the library's load until the
+ * process ends.  The call allocates no device memory (no hipMalloc or
+ * hipFree, no allocating library routine); the caller still provides rows,
+ * cols, blocks and the outputs.  The stream must belong to the current
+ * device.  Every call on one device shares that device's array and leaves
+ * its contents behind (each call clears what it needs cleared): calls that
+ * overlap on one device, e.g. on two streams, race and must be serialised
+ * by the caller.  Limits: as bcsr_assemble, and
+ * bcsr_assemble_workspace_size(n_rows, n_in) <= MAS_NOALLOC_SCRATCH_BYTES
+ * (MAS_WORKSPACE_TOO_SMALL otherwise; nothing is launched).  Synchronises
+ * the stream.  Errors: as bcsr_assemble. */
+int bcsr_assemble_noalloc(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols,
+                          const double* blocks, int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity,
+                          int64_t* nnzb, void* stream);
+
 /* Device bytes of scratch mas_hierarchy_device needs (after mas_analyze). */
 size_t mas_hierarchy_workspace_size(const mas_handle* h);
 

@@ -7,7 +7,7 @@ fails loudly if the library has not been built.
 """
 
 from ._lib import LibraryMissing, MasError, load
-from .solver import BlockMatrix, MasPcg, bcsr_assemble, bcsr_spmv
+from .solver import BlockMatrix, MasPcg, bcsr_assemble, bcsr_assemble_noalloc, bcsr_spmv
 from .autograd import MasPcgSolve, mas_pcg_solve
 from .ordering import morton_codes, morton_partition
 
@@ -16,6 +16,7 @@ __all__ = [
     "MasPcg",
     "bcsr_spmv",
     "bcsr_assemble",
+    "bcsr_assemble_noalloc",
     "MasPcgSolve",
     "mas_pcg_solve",
     "morton_codes",

@@ -4,8 +4,7 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# MASPCG_LIBRARY may name another build of the same library (e.g. a tuning variant).
-LIB_PATH = os.environ.get("MASPCG_LIBRARY") or os.path.join(_HERE, "libmaspcg.so")
+LIB_PATH = os.path.join(_HERE, "libmaspcg.so")
 
 MAS_OK = 0
 MAS_NOT_CONVERGED = 1
@@ -22,6 +21,7 @@ MAS_PRECISION_F64 = 0
 MAS_PRECISION_MIXED = 1
 MAS_MAX_LEVELS = 16
 MAS_MAX_DOMAIN_SIZE = 40
+MAS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 SYMBOLS = (
     "mas_create",
@@ -34,6 +34,7 @@ SYMBOLS = (
     "bcsr_spmv",
     "bcsr_assemble_workspace_size",
     "bcsr_assemble",
+    "bcsr_assemble_noalloc",
     "pcg_solve",
     "pcg_adjoint",
     "mas_hierarchy_workspace_size",
@@ -145,6 +146,9 @@ def load():
     L.bcsr_assemble.argtypes = [i32, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_int64, P(ctypes.c_int64), vp,
                                 ctypes.c_size_t, vp]
     L.bcsr_assemble.restype = ctypes.c_int
+    L.bcsr_assemble_noalloc.argtypes = [i32, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_int64,
+                                        P(ctypes.c_int64), vp]
+    L.bcsr_assemble_noalloc.restype = ctypes.c_int
     L.mas_hierarchy_workspace_size.argtypes = [vp]
     L.mas_hierarchy_workspace_size.restype = ctypes.c_size_t
     L.mas_hierarchy_device.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -661,17 +662,16 @@ size_t bcsr_assemble_workspace_size(int32_t n_rows, int64_t n_in) {
     return total;
 }
 
-int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
-                  int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb,
-                  void* workspace, size_t ws_bytes, void* stream) {
-    if (n_rows < 1 || n_rows + 1 > (1 << 20) || n_in < 0 || n_in > 0x7fffffffLL || capacity < 0 || !nnzb ||
-        !row_ptr || !workspace)
-        return MAS_INVALID_ARG;
-    if (n_in > 0 && (!rows || !cols || !blocks)) return MAS_INVALID_ARG;
-    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
-    if (ws_bytes < bcsr_assemble_workspace_size(n_rows, n_in)) return MAS_WORKSPACE_TOO_SMALL;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const AsmLayout L = assemble_layout(static_cast<char*>(workspace), n_rows, n_in, nullptr);
+}  // extern "C"
+
+namespace {
+
+// bcsr_assemble on scratch memory ws (256-byte aligned, at least
+// bcsr_assemble_workspace_size bytes: checked by the callers).
+int assemble_impl(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
+                  int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb, char* ws,
+                  hipStream_t s) {
+    const AsmLayout L = assemble_layout(ws, n_rows, n_in, nullptr);
     HIP_TRY(launch_assemble_count(L, n_rows, n_in, rows, cols, s));
     HIP_TRY(launch_scan(L.ucnt, n_rows, row_ptr, L.totals, s));
     int host[3] = {0, 0, 0};
@@ -684,6 +684,68 @@ int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
     HIP_TRY(launch_assemble_reduce(L, n_rows, blocks, row_ptr, col_idx, val, s));
     HIP_TRY(hipStreamSynchronize(s));
     return MAS_OK;
+}
+
+bool assemble_args_ok(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
+                      int32_t* row_ptr, int64_t capacity, int64_t* nnzb) {
+    if (n_rows < 1 || n_rows + 1 > (1 << 20) || n_in < 0 || n_in > 0x7fffffffLL || capacity < 0 || !nnzb ||
+        !row_ptr)
+        return false;
+    return n_in == 0 || (rows && cols && blocks);
+}
+
+// Scratch of bcsr_assemble_noalloc.  Each device the library runs on holds
+// its own copy from the code object's load until the process ends.  Host
+// code never passes the array's name to a kernel or a copy (on the host it
+// only stands for the symbol): it looks up the device address once per
+// device and uses that.
+__device__ __align__(256) char scratch[MAS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch (looked up on the first
+// call on that device, with it current).
+int noalloc_scratch(char** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return MAS_HIP_ERROR;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MAS_HIP_ERROR;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<char*>(g_scratch_ptr[dev]);
+    return MAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
+                  int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb,
+                  void* workspace, size_t ws_bytes, void* stream) {
+    if (!assemble_args_ok(n_rows, n_in, rows, cols, blocks, row_ptr, capacity, nnzb) || !workspace)
+        return MAS_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < bcsr_assemble_workspace_size(n_rows, n_in)) return MAS_WORKSPACE_TOO_SMALL;
+    return assemble_impl(n_rows, n_in, rows, cols, blocks, row_ptr, col_idx, val, capacity, nnzb,
+                         static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+}
+
+int bcsr_assemble_noalloc(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols,
+                          const double* blocks, int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity,
+                          int64_t* nnzb, void* stream) {
+    if (!assemble_args_ok(n_rows, n_in, rows, cols, blocks, row_ptr, capacity, nnzb)) return MAS_INVALID_ARG;
+    if (bcsr_assemble_workspace_size(n_rows, n_in) > MAS_NOALLOC_SCRATCH_BYTES) return MAS_WORKSPACE_TOO_SMALL;
+    char* ws = nullptr;
+    const int rc = noalloc_scratch(&ws);
+    if (rc != MAS_OK) return rc;
+    return assemble_impl(n_rows, n_in, rows, cols, blocks, row_ptr, col_idx, val, capacity, nnzb, ws,
+                         static_cast<hipStream_t>(stream));
 }
 
 namespace {

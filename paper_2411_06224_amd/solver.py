@@ -127,6 +127,29 @@ def bcsr_assemble(n_rows, rows, cols, blocks, capacity=None):
     raise MasError("bcsr_assemble", MAS_INVALID_ARG)
 
 
+def bcsr_assemble_noalloc(n_rows, rows, cols, blocks, row_ptr, col_idx, val):
+    """bcsr_assemble into caller-allocated outputs, with the library's
+    static device scratch instead of a workspace (no device allocation in
+    the call).  row_ptr: int32 [n_rows + 1]; col_idx: int32 [capacity];
+    val: float64 [capacity, 3, 3].  Returns the number of distinct blocks."""
+    _need_cuda(rows, "rows", torch.int32)
+    _need_cuda(cols, "cols", torch.int32)
+    _need_cuda(blocks, "blocks", torch.float64)
+    _need_cuda(row_ptr, "row_ptr", torch.int32)
+    _need_cuda(col_idx, "col_idx", torch.int32)
+    _need_cuda(val, "val", torch.float64)
+    m = rows.numel()
+    if cols.numel() != m or blocks.numel() != 9 * m:
+        raise ValueError("rows, cols and blocks must describe the same number of blocks")
+    if row_ptr.numel() != int(n_rows) + 1 or val.numel() != 9 * col_idx.numel():
+        raise ValueError("row_ptr must hold n_rows + 1 entries and val 9 values per col_idx entry")
+    nb = ctypes.c_int64(0)
+    rc = _lib.load().bcsr_assemble_noalloc(int(n_rows), m, _ptr(rows), _ptr(cols), _ptr(blocks), _ptr(row_ptr),
+                                           _ptr(col_idx), _ptr(val), col_idx.numel(), ctypes.byref(nb), _stream())
+    check("bcsr_assemble_noalloc", rc)
+    return int(nb.value)
+
+
 class MasPcg:
     """MAS-preconditioned PCG for one sparsity pattern.
 
