@@ -74,21 +74,28 @@ def algorithmic_bytes(info, mixed):
     coarse_y = sum(8 * 3 * info["domains"][l] * N for l in range(1, L))
     # level-0 inverses: FP64 symmetric-packed for N = 16 (n (n + 1) / 2 entries), else full
     inv0 = info["domains"][0] * (n * (n + 1) // 2 if (N == 16 and not mixed) else n * n) * inv
+    r1b = 8 * 3 * info["units"][1] if L > 1 else 0  # one level-1 vector
+    if mixed:  # the FP32 copy keeps every block: values, column index, row pointers
+        stored = nnzb * (val + 4) + 4 * (NS + 1)
+    else:  # symmetric FP64 storage: values, column index and local row of each stored block,
+        # row pointers and transposed-entry lists
+        stored = nsb * (val + 4 + 1) + 8 * (NS + 1) + 4 * (nnzb - nsb)
     out = {
-        # stored blocks (each block pair inside a work group once): values,
-        # column index and local row; row pointers and transposed-entry lists;
-        # z and the previous direction read once (the direction update is
-        # fused in), new direction and q written
-        "spmv": nsb * (val + 4 + 1) + 8 * (NS + 1) + 4 * (nnzb - nsb) + 4 * vb,
+        # the stored matrix; z and the previous direction read once (the
+        # direction update is fused in), new direction and q written; the
+        # restriction of q: per-slot plan (16 B) read, q_1 written
+        "spmv": stored + 4 * vb + 16 * NS + r1b,
         # level-0 inverses, r read, z written, per-slot coarse ids, coarse corrections
         "apply_level0": inv0 + 2 * vb + 4 * (L - 1) * NS + coarse_y,
-        # coarse inverses, restricted residual read, y written
-        "apply_coarse": sum(info["domains"][l] * n * n * inv for l in range(1, L))
-        + (8 * 3 * info["units"][1] if L > 1 else 0)
-        + coarse_y,
+        # coarse inverses, restricted residual read (and, by recurrence, q_1
+        # read and r_1 written), y written
+        "apply_coarse": sum(info["domains"][l] * n * n * inv for l in range(1, L)) + 3 * r1b + coarse_y,
         # x, r read+write, p, q read, per-slot plan ints, r_1 written
         "update": 6 * vb + 8 * NS + (8 * 3 * info["units"][1] if L > 1 else 0),
     }
+    # level-0 apply fused with the x/r update: also x read and written, r
+    # written, p and q read
+    out["level0_update"] = out["apply_level0"] + 5 * vb
     return out
 
 
@@ -102,6 +109,8 @@ def main():
     ap.add_argument("--domain-size", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / adjoint / instrumented runs")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (8^3 cube, E / tol sweep, mixed, membrane, adjoint at E = 1e7)")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -157,9 +166,11 @@ def main():
         _, res = step(solver, args.tol)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters = []
+    iters, step_ms = [], []
     for _ in range(args.steps):
-        _, res = step(solver, args.tol)
+        ts = time.perf_counter()
+        _, res = step(solver, args.tol)  # the solve returns once the device is done
+        step_ms.append(1e3 * (time.perf_counter() - ts))
         iters.append(res["iterations"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -194,6 +205,7 @@ def main():
             "supernodes": info["units"][1:],
             "parallelism": "single GPU",
         },
+        "median_ms_per_step": round(float(np.median(step_ms)), 4),
         "iterations": iters[-1],
         "true_rel_residual": res["true_rel_residual"],
         "phase_ms": {
@@ -235,7 +247,14 @@ def main():
             "traffic": measured_traffic(dom),
             "alg_bytes_per_launch": nbytes[dom],
             "avg_launch_us": per[dom]["avg_us"],
+            "launches_averaged": per[dom]["launches"],
         }
+        if dom == "spmv":
+            # the same launches priced at the bytes of plain full 3x3-block CSR
+            # (every block's values, column index, row pointers, x read, y written)
+            full = s.nnzb * (72 + 4) + 4 * (s.n + 1) + 2 * 8 * 3 * s.n
+            out["roofline"]["frac_on_full_bcsr_bytes"] = round(full / (per[dom]["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+            out["roofline"]["full_bcsr_bytes"] = full
         out["kernels"] = per
         log("kernels:", json.dumps(per))
         # the paper's breakdown of a solve (Table 1 columns): preconditioner
@@ -245,8 +264,9 @@ def main():
         tot = {k: kt[k][0] for k in kt}
         out["paper_breakdown_ms"] = {
             "PPC": round(ph[0] + ph[1], 4),
-            "PPR": round(tot.get("apply_coarse", 0.0) + tot.get("apply_level0", 0.0), 4),
+            "PPR": round(tot.get("apply_coarse", 0.0) + tot.get("apply_level0", 0.0) + tot.get("level0_update", 0.0), 4),
             "CGR": round(tot.get("spmv", 0.0) + tot.get("update", 0.0) + tot.get("residual", 0.0), 4),
+            "note": "the level-0 apply fused with the x/r update counts as PPR",
         }
 
         # achievable HBM bandwidth for context: a triad a = b + s c over three
@@ -268,6 +288,24 @@ def main():
         out["roofline"]["achievable_triad_GBs"] = round(triad, 1)
         out["roofline"]["frac_of_triad"] = round(ach / triad, 4)
         log(f"triad: {triad:.0f} GB/s")
+        # the same triad on three 48 MiB arrays (144 MiB, within the 256 MB
+        # last-level cache, about the size of the solver's working set),
+        # repeated so that the arrays stay cache-resident
+        nm = (48 << 20) // 8
+        ta, tb, tc = (torch.empty(nm, dtype=torch.float64, device=dev) for _ in range(3))
+        tb.fill_(1.0)
+        tc.fill_(2.0)
+        for _ in range(5):
+            torch.add(tb, tc, alpha=0.5, out=ta)
+        e0.record()
+        for _ in range(100):
+            torch.add(tb, tc, alpha=0.5, out=ta)
+        e1.record()
+        torch.cuda.synchronize()
+        triad_c = 3 * nm * 8 * 100 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        del ta, tb, tc
+        out["roofline"]["triad_144MiB_GBs"] = round(triad_c, 1)
+        log(f"triad on 144 MiB: {triad_c:.0f} GB/s")
 
         # batched domain inversion: about (3N)^3 flops per domain (FP64, MFMA)
         n3 = (3 * info["domain_size"]) ** 3
@@ -295,7 +333,23 @@ def main():
             "true_rel_residual": mres["true_rel_residual"],
             "speedup_vs_f64": round(ms_per_step / ms_mixed, 3),
         }
+        x_mixed = x.cpu().numpy()
         log(f"mixed solve: {ms_mixed:.3f} ms, {mres['iterations']} its, true res {mres['true_rel_residual']:.3e}")
+        # per-kernel times of the mixed solve against the FP64 ones
+        msolver.set_kernel_timing(True)
+        step(msolver, args.tol)
+        mkt = msolver.kernel_timing()
+        msolver.set_kernel_timing(False)
+        mbytes = algorithmic_bytes(msolver.info(), mixed=True)
+        mper = {}
+        for k, nb in mbytes.items():
+            tot, cnt = mkt[k]
+            if cnt:
+                avg = tot / cnt
+                mper[k] = {"avg_us": round(avg * 1e3, 3), "launches": cnt, "alg_bytes": nb,
+                           "GBs": round(nb / (avg * 1e-3) / 1e9, 1)}
+        out["mixed"]["kernels"] = mper
+        log("mixed kernels:", json.dumps(mper))
         msolver.close()
 
         # assembly of the system from its unassembled block list (element,
@@ -406,32 +460,220 @@ def main():
         log(f"fwd+adjoint: {ms_fb:.3f} ms ({ms_fb / ms_per_step:.2f}x)")
 
     if not args.no_cpu_baseline:
-        import oracle
-
-        ncores = os.cpu_count()
-        t0 = time.perf_counter()
-        P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=args.domain_size, gptr=s.gptr, gadj=s.gadj)
-        t_build = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        xo, st, it, rr, tr = P.pcg(s.b, tol=args.tol)
-        t_pcg = time.perf_counter() - t0
+        ncores = len(os.sched_getaffinity(0))
+        t_build, t_pcg, it, xo, core = oracle_solve(s, args.domain_size, args.tol)
         out["cpu_baseline"] = {
             "value": round(1e3 * (t_build + t_pcg), 1),
             "unit": "ms",
             "cores": 1,
             "kind": "oracle",
             "sample": f"the whole workload once: oracle partition+hierarchy+inversion ({t_build:.2f} s) and PCG "
-            f"to {args.tol:g} ({it} iterations, {t_pcg:.2f} s), single-threaded C on 1 of {ncores} host cores",
+            f"to {args.tol:g} ({it} iterations, {t_pcg:.2f} s), single-threaded C pinned to core {core}, "
+            f"1 of {ncores} host cores ({cpu_model()})",
             "iterations": it,
+            "cpu_model": cpu_model(),
         }
         log(f"cpu oracle: build {t_build:.2f}s pcg {t_pcg:.2f}s ({it} its)")
-        xg = x.cpu().numpy()
         solver.build(H)
         xg = solver.solve(H, b, tol=args.tol)[0].cpu().numpy()
         out["gpu_vs_oracle_rel_err"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        if "mixed" in out:
+            out["mixed"]["rel_err_vs_f64_oracle"] = float(np.linalg.norm(x_mixed - xo) / np.linalg.norm(xo))
+
+    if not args.no_configs:
+        out["configs"] = run_configs(args, s, H, b, dev, x_oracle=None if args.no_cpu_baseline else xo)
 
     print(json.dumps(out), flush=True)
     solver.close()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_solve(s, N, tol, max_levels=0):
+    """The CPU oracle on system s (single-threaded C), pinned to the first
+    host core this process may use: (build s, pcg s, iterations, x, core)."""
+    import oracle
+
+    prev = os.sched_getaffinity(0)
+    core = min(prev)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=N, max_levels=max_levels, gptr=s.gptr, gadj=s.gadj)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        xo, st, it, rr, tr = P.pcg(s.b, tol=tol)
+        t_pcg = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, prev)
+    return t_build, t_pcg, it, xo, core
+
+
+def gpu_solves(mp, s, H, b, tol, steps, precision="f64", max_levels=0, N=16):
+    """Build + solve steps times after two warm-ups: mean and median ms, the
+    last result and x."""
+    import numpy as np
+    import torch
+
+    sv = mp.MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=N, precision=precision,
+                   max_levels=max_levels)
+    x = torch.empty_like(b)
+    for _ in range(2):
+        sv.build(H)
+        sv.solve(H, b, tol=tol, out=x)
+    ms = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        sv.build(H)
+        _, res = sv.solve(H, b, tol=tol, out=x)
+        ms.append(1e3 * (time.perf_counter() - t0))
+    sv.close()
+    if res["status"] != 0:
+        raise SystemExit(f"solve did not converge: {res}")
+    return float(np.mean(ms)), float(np.median(ms)), res, x
+
+
+def run_configs(args, s1, H1, b1, dev, x_oracle):
+    """The other workloads of the benchmark set, each timed on the GPU
+    (build + solve, mean and median of the steps) with its iteration count
+    and FP64 true residual, and the CPU oracle on the same system once
+    (pinned to one core)."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2411_06224_amd as mp
+
+    steps = max(3, min(args.steps, 10))
+    cfg = {}
+
+    def gpu_entry(mean, med, res):
+        return {"ms": round(mean, 4), "median_ms": round(med, 4), "iterations": res["iterations"],
+                "true_rel_residual": res["true_rel_residual"]}
+
+    def with_oracle(entry, s, tol, max_levels=0):
+        tb, tp, it, xo, _ = oracle_solve(s, 16, tol, max_levels)
+        entry["oracle"] = {"ms": round(1e3 * (tb + tp), 1), "iterations": it, "cores": 1}
+        return xo
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    # 8^3 cube, two-level MAS, FP64 to 1e-8: latency-bound, so us per iteration
+    s0 = synth.config_small()
+    H0 = mp.BlockMatrix.from_numpy(s0.row_ptr, s0.col_idx, s0.val, device=dev)
+    b0 = torch.as_tensor(s0.b, device=dev)
+    mean, med, res, _ = gpu_solves(mp, s0, H0, b0, 1e-8, 20, max_levels=2)
+    e = gpu_entry(mean, med, res)
+    e["us_per_iteration"] = round(1e3 * med / max(res["iterations"], 1), 2)
+    with_oracle(e, s0, 1e-8, max_levels=2)
+    cfg["cube8_f64_tol1e-8"] = e
+    log("cube8:", json.dumps(e))
+
+    # 48^3 at E = 1e6: FP64 to 1e-8, mixed to 1e-4 and 1e-6 (error against the
+    # FP64 oracle's solution at the same tolerance)
+    mean, med, res, _ = gpu_solves(mp, s1, H1, b1, 1e-8, steps)
+    e = gpu_entry(mean, med, res)
+    with_oracle(e, s1, 1e-8)
+    cfg["cube48_E1e6_f64_tol1e-8"] = e
+    log("cube48 E=1e6 1e-8:", json.dumps(e))
+    for tol in (1e-4, 1e-6):
+        mean, med, res, xm = gpu_solves(mp, s1, H1, b1, tol, steps, precision="mixed")
+        e = gpu_entry(mean, med, res)
+        xo = x_oracle if (tol == 1e-4 and x_oracle is not None) else with_oracle(e, s1, tol)
+        e["rel_err_vs_f64_oracle"] = rel(xm.cpu().numpy(), xo)
+        cfg[f"cube48_E1e6_mixed_tol{tol:g}"] = e
+        log(f"cube48 E=1e6 mixed {tol:g}:", json.dumps(e))
+
+    # 48^3 at E = 1e4 and 1e8 (FP64 to 1e-4; mixed at E = 1e8 to 1e-4, 1e-6)
+    for E in (1e4, 1e8):
+        sE = synth.config_large(E=E)
+        HE = mp.BlockMatrix.from_numpy(sE.row_ptr, sE.col_idx, sE.val, device=dev)
+        bE = torch.as_tensor(sE.b, device=dev)
+        mean, med, res, _ = gpu_solves(mp, sE, HE, bE, 1e-4, steps)
+        e = gpu_entry(mean, med, res)
+        xo4 = with_oracle(e, sE, 1e-4)
+        cfg[f"cube48_E{E:g}_f64_tol1e-4"] = e
+        log(f"cube48 E={E:g}:", json.dumps(e))
+        if E == 1e8:
+            f64_ms = mean
+            # hierarchy depth at this stiffness: block Jacobi over the level-0
+            # domains (1 level), two levels, all levels
+            depth = {}
+            for ml in (1, 2):
+                dm, dmed, dres, _ = gpu_solves(mp, sE, HE, bE, 1e-4, steps, max_levels=ml)
+                depth[f"max_levels_{ml}"] = {"ms": round(dm, 4), "iterations": dres["iterations"]}
+            depth["all_levels"] = {"ms": round(f64_ms, 4), "iterations": cfg[f"cube48_E{E:g}_f64_tol1e-4"]["iterations"]}
+            cfg["cube48_E1e8_depth_ablation"] = depth
+            log("cube48 E=1e8 depth:", json.dumps(depth))
+            for tol in (1e-4, 1e-6):
+                mean, med, res, xm = gpu_solves(mp, sE, HE, bE, tol, steps, precision="mixed")
+                e = gpu_entry(mean, med, res)
+                xo = xo4 if tol == 1e-4 else with_oracle(e, sE, tol)
+                e["rel_err_vs_f64_oracle"] = rel(xm.cpu().numpy(), xo)
+                if tol == 1e-4:
+                    e["speedup_vs_f64"] = round(f64_ms / mean, 3)
+                cfg[f"cube48_E{E:g}_mixed_tol{tol:g}"] = e
+                log(f"cube48 E={E:g} mixed {tol:g}:", json.dumps(e))
+        del HE, bE, sE
+
+    # 48^3 at E = 1e7: mixed forward to 1e-6, then the adjoint solve with
+    # dL/dH in FP32 for L = 1/2 ||x - x*||^2
+    s7 = synth.config_large(E=1e7)
+    H7 = mp.BlockMatrix.from_numpy(s7.row_ptr, s7.col_idx, s7.val, device=dev)
+    b7 = torch.as_tensor(s7.b, device=dev)
+    sv = mp.MasPcg(s7.row_ptr, s7.col_idx, graph=(s7.gptr, s7.gadj), domain_size=16, precision="mixed")
+    xt = torch.as_tensor(np.random.default_rng(4).standard_normal(3 * s7.n), device=dev)
+    x7 = torch.empty_like(b7)
+    fwd, both = [], []
+    for i in range(steps + 2):
+        t0 = time.perf_counter()
+        sv.build(H7)
+        _, fres = sv.solve(H7, b7, tol=1e-6, out=x7)
+        t1 = time.perf_counter()
+        _, _, ares = sv.adjoint(H7, x7, x7 - xt, dLdH_dtype=torch.float32, tol=1e-6)
+        t2 = time.perf_counter()
+        if i >= 2:
+            fwd.append(1e3 * (t1 - t0))
+            both.append(1e3 * (t2 - t0))
+    sv.close()
+    cfg["cube48_E1e7_mixed_fwd_adjoint_tol1e-6"] = {
+        "ms_forward": round(float(np.mean(fwd)), 4),
+        "ms_forward_plus_adjoint": round(float(np.mean(both)), 4),
+        "ratio": round(float(np.mean(both) / np.mean(fwd)), 3),
+        "forward_iterations": fres["iterations"],
+        "adjoint_iterations": ares["iterations"],
+        "forward_true_rel_residual": fres["true_rel_residual"],
+    }
+    log("cube48 E=1e7 fwd+adjoint:", json.dumps(cfg["cube48_E1e7_mixed_fwd_adjoint_tol1e-6"]))
+    del H7, b7, s7
+
+    # stiff membrane (512^2 cells) + 2,000 affine bodies: FP64 and mixed to 1e-4
+    sm = synth.config_membrane()
+    Hm = mp.BlockMatrix.from_numpy(sm.row_ptr, sm.col_idx, sm.val, device=dev)
+    bm = torch.as_tensor(sm.b, device=dev)
+    mean, med, res, _ = gpu_solves(mp, sm, Hm, bm, 1e-4, steps)
+    e = gpu_entry(mean, med, res)
+    xo = with_oracle(e, sm, 1e-4)
+    cfg["membrane512_bodies2000_f64_tol1e-4"] = e
+    f64_ms = mean
+    log("membrane f64:", json.dumps(e))
+    mean, med, res, xm = gpu_solves(mp, sm, Hm, bm, 1e-4, steps, precision="mixed")
+    e = gpu_entry(mean, med, res)
+    e["rel_err_vs_f64_oracle"] = rel(xm.cpu().numpy(), xo)
+    e["speedup_vs_f64"] = round(f64_ms / mean, 3)
+    cfg["membrane512_bodies2000_mixed_tol1e-4"] = e
+    log("membrane mixed:", json.dumps(e))
+    return cfg
 
 
 if __name__ == "__main__":

@@ -90,7 +90,9 @@ typedef struct {
     double tol;              /* stop when ||r||_2 <= tol * ||b||_2 */
     int32_t max_iter;        /* >= 0 */
     int32_t x0_given;        /* 1: x holds the initial guess, else x0 = 0 */
-    int32_t replace_every;   /* mixed mode: FP64 residual replacement period (0 -> 50) */
+    int32_t replace_every;   /* period of the iterations that restrict the residual itself rather
+                                than updating its coarse restriction by recurrence, and in mixed
+                                mode of the FP64 residual replacement (0 -> 50) */
     int32_t check_every;     /* iterations between host convergence checks (0 -> 8) */
 } pcg_options;
 
@@ -316,11 +318,13 @@ int mas_get_timings(const mas_handle* h, double* ms4);
 int mas_set_kernel_timing(mas_handle* h, int enable);
 
 /* Totals since the last mas_set_kernel_timing: total_ms[8] and launches[8]
- * for the kernel slots [0] direction update and SpMV q = H p with p^T q, [1] x/r update with
- * ||r||^2 and restriction to level 1, [2] coarse-level MAS apply,
- * [3] level-0 MAS apply with prolongation and r^T z, [4] reserved (0; the
- * direction update p = z + beta p runs inside [0]), [5] FP64 residual
- * replacement, [6] permutation of H, [7] restriction only.  Host arrays. */
+ * for the kernel slots [0] direction update and SpMV q = H p with p^T q
+ * (and the restriction of q), [1] x/r update with ||r||^2 and the
+ * restriction of r, [2] coarse-level MAS apply, [3] level-0 MAS apply with
+ * prolongation and r^T z, [4] the same fused with the x/r update,
+ * [5] FP64 residual replacement, [6] permutation of H, [7] restriction only.
+ * Launches queued after the solve had stopped, which return at once, are
+ * not counted.  Host arrays. */
 int mas_get_kernel_timing(const mas_handle* h, double* total_ms, int32_t* launches);
 
 /* Short English description of a status code (static string). */

@@ -13,6 +13,7 @@
 #include "../../include/mas_pcg.h"
 #include "launch.hpp"
 #include "planner.hpp"
+#include "restrict.hpp"
 
 using namespace maspcg;
 
@@ -24,9 +25,9 @@ struct Layout {
     size_t total = 0;
     size_t remap, map, perm_src, perm_full, rp0, ci0, lead1, anc, g_u1, srp, sci, srow, tptr, tidx;
     size_t red_ptr[kMaxLv], red_src[kMaxLv], dom_ptr[kMaxLv], dom_blk[kMaxLv], dom_ab[kMaxLv];
-    size_t ganc, gpos, gmask, cp_ptr[kMaxLv], lmask, gorder;
+    size_t ganc, gpos, gmask, cp_ptr[kMaxLv], lmask, gorder, gu1_slot, gu1_mask, gw_pos, gw_li, gw_mask;
     size_t H64, H32, A[kMaxLv], inv64[kMaxLv], inv32[kMaxLv];
-    size_t b, x, r, z, p0, p1, q, r1, y[kMaxLv], cpart, P_sigma, P_rr, P_bb, P_rho0, P_rho1, st, flag;
+    size_t b, x, r, z, p0, p1, q, r1, q1, y[kMaxLv], rc[kMaxLv], cpart, qpart, P_sigma, P_rr, P_bb, P_rho0, P_rho1, st, flag;
     size_t inverse_bytes = 0;
 
     size_t take(size_t bytes) {
@@ -39,13 +40,22 @@ struct Layout {
 enum { kEvBuild0 = 0, kEvBuild1, kEvBuild2, kEvSolve0, kEvSolve1, kEvSolve2, kEvPoll0, kEvPoll1, kEvCount };
 
 // Kernel slots of the optional per-launch timing (mas_set_kernel_timing).
-enum { kKSpmv = 0, kKUpdate, kKCoarse, kKLevel0, kKUpdateP, kKResidual, kKPermute, kKRestrict, kKSlots };
+enum { kKSpmv = 0, kKUpdate, kKCoarse, kKLevel0, kKLevel0Upd, kKResidual, kKPermute, kKRestrict, kKSlots };
+
+// Per-launch timing entries: the kernel slot and a tag that orders the
+// launch against the convergence decisions: 2k for the launches of
+// iteration k up to the decision on r_k, 2k + 1 after it, -1 outside the
+// iteration.  Launches tagged above 2K, K the iteration the solve stopped
+// at, were queued past the stop and returned at once; they are left out.
+struct TimedLaunch {
+    int slot, tag;
+};
 
 struct KernelTimer {
     bool on = false;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    std::vector<int> pending;  // kernel slot of each started pair
+    std::vector<TimedLaunch> pending;  // one per started pair
     double total_ms[kKSlots] = {0};
     int launches[kKSlots] = {0};
 };
@@ -64,6 +74,7 @@ struct mas_handle {
     size_t ws_size = 0;
     char* uploaded_to = nullptr;
     bool built = false;
+    bool fuse_ok = false;  // the SpMV kernels can stage the restriction of q (three launches per iteration)
     DevState* st_host = nullptr;  // pinned: [0] last blocking read, [1..2] per-batch copies
     int* flag_host = nullptr;     // pinned
     hipEvent_t ev[kEvCount]{};
@@ -83,7 +94,7 @@ namespace {
 // the runtime stamps with that dispatch's own start and end (resolved at the
 // next synchronisation).
 template <typename F>
-hipError_t timed(mas_handle* h, int slot, hipStream_t s, F&& launch) {
+hipError_t timed(mas_handle* h, int slot, hipStream_t s, F&& launch, int tag = -1) {
     (void)s;
     KernelTimer& t = h->kt;
     if (!t.on) return launch();
@@ -103,19 +114,22 @@ hipError_t timed(mas_handle* h, int slot, hipStream_t s, F&& launch) {
     if (err != hipSuccess) return err;
     if (launched) {
         t.used += 2;
-        t.pending.push_back(slot);
+        t.pending.push_back(TimedLaunch{slot, tag});
     }
     return hipSuccess;
 }
 
-// Called after the stream has been synchronised.
-void collect_timing(mas_handle* h) {
+// Called after the stream has been synchronised; last_iter: the iteration
+// count of the device state just read.
+void collect_timing(mas_handle* h, int last_iter) {
     KernelTimer& t = h->kt;
     for (size_t k = 0; k < t.pending.size(); ++k) {
+        const TimedLaunch& e = t.pending[k];
+        if (e.tag > 2 * last_iter) continue;  // queued past the stop: returned at once
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, t.pool[2 * k], t.pool[2 * k + 1]) == hipSuccess) {
-            t.total_ms[t.pending[k]] += ms;
-            t.launches[t.pending[k]] += 1;
+            t.total_ms[e.slot] += ms;
+            t.launches[e.slot] += 1;
         }
     }
     t.pending.clear();
@@ -147,6 +161,11 @@ void make_layout(mas_handle* h) {
     Y.lmask = Y.take(sizeof(uint64_t) * P.NS);
     Y.anc = Y.take(I * P.anc.size());
     Y.g_u1 = Y.take(I * P.g_u1.size());
+    Y.gu1_slot = Y.take(I * P.gu1_slot.size());
+    Y.gu1_mask = Y.take(sizeof(uint64_t) * P.gu1_mask.size());
+    Y.gw_pos = Y.take(I * P.gw_pos.size());
+    Y.gw_li = Y.take(I * P.gw_li.size());
+    Y.gw_mask = Y.take(sizeof(uint64_t) * P.gw_mask.size());
     Y.gorder = Y.take(I * P.gorder.size());
     const size_t gtab = P.L > 2 ? static_cast<size_t>(P.G) * (P.L - 2) * P.W1 : 0;  // [G][L-2][W1]
     Y.ganc = Y.take(I * gtab);
@@ -189,8 +208,11 @@ void make_layout(mas_handle* h) {
     Y.p1 = Y.take(vec);
     Y.q = Y.take(vec);
     Y.r1 = Y.take(Dd * 3 * (P.L > 1 ? P.units[1] : 1));
+    Y.q1 = Y.take(Dd * 3 * (P.L > 1 ? P.units[1] : 1));
     for (int l = 1; l < P.L; ++l) Y.y[l] = Y.take(Dd * 3 * static_cast<size_t>(P.ndom[l]) * P.N);
+    for (int l = 2; l < P.L; ++l) Y.rc[l] = Y.take(Dd * 3 * static_cast<size_t>(P.ndom[l]) * P.N);
     Y.cpart = Y.take(Dd * 3 * std::max(P.n_cpart, 1));
+    Y.qpart = Y.take(Dd * 3 * std::max(P.n_cpart, 1));
     Y.P_sigma = Y.take(Dd * P.G);
     Y.P_rr = Y.take(Dd * P.G);
     Y.P_bb = Y.take(Dd * P.G);
@@ -232,13 +254,22 @@ SolverView view(const mas_handle* h) {
         v.inv32[l] = h->opts.precision == MAS_PRECISION_MIXED ? at<float>(h, Y.inv32[l]) : nullptr;
         if (l >= 2) v.cp_ptr[l] = at<int>(h, Y.cp_ptr[l]);
         if (l >= 1) v.y[l] = at<double>(h, Y.y[l]);
+        if (l >= 2) v.rc[l] = at<double>(h, Y.rc[l]);
     }
     v.g_u1 = at<int>(h, Y.g_u1);
+    v.gu1_slot = at<int>(h, Y.gu1_slot);
+    v.gu1_mask = at<uint64_t>(h, Y.gu1_mask);
+    v.GW = P.GW;
+    v.rfast = restrict_fast_ok(P.W1, P.GW, spmv_threads()) ? 1 : 0;
+    v.gw_pos = at<int>(h, Y.gw_pos);
+    v.gw_li = at<int>(h, Y.gw_li);
+    v.gw_mask = at<uint64_t>(h, Y.gw_mask);
     v.gorder = P.gorder.empty() ? nullptr : at<int>(h, Y.gorder);
     v.ganc = at<int>(h, Y.ganc);
     v.gpos = at<int>(h, Y.gpos);
     v.gmask = at<uint64_t>(h, Y.gmask);
     v.cpart = at<double>(h, Y.cpart);
+    v.qpart = at<double>(h, Y.qpart);
     v.P_sigma = at<double>(h, Y.P_sigma);
     v.P_rr = at<double>(h, Y.P_rr);
     v.P_bb = at<double>(h, Y.P_bb);
@@ -263,6 +294,7 @@ SolverView view(const mas_handle* h) {
     v.p[1] = at<double>(h, Y.p1);
     v.q = at<double>(h, Y.q);
     v.r1 = at<double>(h, Y.r1);
+    v.q1 = at<double>(h, Y.q1);
     v.st = at<DevState>(h, Y.st);
     v.flag = at<int>(h, Y.flag);
     return v;
@@ -321,6 +353,13 @@ int upload_plan(mas_handle* h, hipStream_t s) {
                            s));
     HIP_TRY(put(Y.anc, P.anc));
     HIP_TRY(put(Y.g_u1, P.g_u1));
+    HIP_TRY(put(Y.gu1_slot, P.gu1_slot));
+    HIP_TRY(hipMemcpyAsync(h->ws + Y.gu1_mask, P.gu1_mask.data(), sizeof(uint64_t) * P.gu1_mask.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(put(Y.gw_pos, P.gw_pos));
+    HIP_TRY(put(Y.gw_li, P.gw_li));
+    HIP_TRY(hipMemcpyAsync(h->ws + Y.gw_mask, P.gw_mask.data(), sizeof(uint64_t) * P.gw_mask.size(),
+                           hipMemcpyHostToDevice, s));
     if (!P.gorder.empty()) HIP_TRY(put(Y.gorder, P.gorder));
     for (int l = 0; l < P.L; ++l) {
         if (l >= 1) {
@@ -368,27 +407,36 @@ int finish_status(const DevState& st) {
     return MAS_NOT_CONVERGED;
 }
 
+// The MAS apply of iteration k after the residual's direct restriction:
+// coarse levels with the decision on r_k, then level 0.
 hipError_t apply_iter(mas_handle* h, const SolverView& v, bool mixed, int k, bool rr_true, hipStream_t s) {
     hipError_t e;
-    if ((e = timed(h, kKCoarse, s, [&] {
-             return launch_apply_coarse(v, mixed, kApplyIter, k, 0.0, false, mixed, rr_true, s);
-         })) != hipSuccess)
+    if ((e = timed(
+             h, kKCoarse, s,
+             [&] { return launch_apply_coarse(v, mixed, kApplyIter, k, 0.0, false, mixed, rr_true, s); },
+             2 * k)) != hipSuccess)
         return e;
-    return timed(h, kKLevel0, s, [&] { return launch_apply_level0(v, mixed, kApplyIter, k, s); });
+    return timed(h, kKLevel0, s, [&] { return launch_apply_level0(v, mixed, kApplyIter, k, s); }, 2 * k + 1);
 }
 
 int read_state(mas_handle* h, const SolverView& v, hipStream_t s) {
     HIP_TRY(hipMemcpyAsync(h->st_host, v.st, sizeof(DevState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    collect_timing(h);
+    collect_timing(h, h->st_host[0].iter);
     return MAS_OK;
 }
 
-// The PCG driver shared by pcg_solve and pcg_adjoint.  Iteration k:
-//   p = z + beta p and q = H p (sigma partials) -> alpha, x += alpha p,
-//   r -= alpha q (||r||^2 partials, restriction) -> [mixed: FP64 residual
-//   replacement] -> convergence test and coarse apply -> level-0 apply and
-//   prolongation (rho partials).
+// The PCG driver shared by pcg_solve and pcg_adjoint.  Iteration k takes
+// three launches:
+//   p = z + beta p, q = H p (sigma partials) and the restriction of q ->
+//   convergence test on r_{k-1}, alpha, C_l r_k = C_l r_{k-1} - alpha C_l q_k
+//   and the coarse apply -> x += alpha p, r -= alpha q (||r||^2 partials),
+//   level-0 apply and prolongation (rho partials);
+// every replace_every-th iteration (and every iteration when the SpMV cannot
+// lend shared memory to the restriction) restricts r_k itself instead:
+//   SpMV -> x/r update with the restriction of r_k -> [mixed: FP64 residual
+//   replacement] -> convergence test on r_k and coarse apply -> level-0
+//   apply, which also bounds the rounding the recurrence accumulates.
 // The host reads the state every check_every iterations; iterations queued
 // after a stop return at once.
 int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, const pcg_options* o, pcg_result* res,
@@ -426,18 +474,33 @@ int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, con
     // state is copied into a pinned slot; the host looks at a batch's copy
     // only once the next batch is queued, so the device never waits for the
     // host.  Kernels queued after a stop return at once.
+    auto direct = [&](int kk) { return !h->fuse_ok || kk % opt.replace_every == 0; };
     auto batch = [&](int nb) -> int {
         for (int i = 0; i < nb; ++i) {
             ++k;
-            HIP_TRY(timed(h, kKSpmv, s, [&] { return launch_spmv_pq(v, mixed, k, s); }));
-            HIP_TRY(timed(h, kKUpdate, s, [&] { return launch_update(v, k, s); }));
+            if (!direct(k)) {
+                HIP_TRY(timed(h, kKSpmv, s, [&] { return launch_spmv_pq(v, mixed, k, true, s); }, 2 * k));
+                HIP_TRY(timed(
+                    h, kKCoarse, s,
+                    [&] { return launch_apply_coarse(v, mixed, kApplyRec, k, 0.0, false, mixed, false, s); },
+                    2 * k));
+                HIP_TRY(timed(h, kKLevel0Upd, s, [&] { return launch_apply_level0(v, mixed, kApplyRec, k, s); },
+                              2 * k));
+                continue;
+            }
+            HIP_TRY(timed(h, kKSpmv, s, [&] { return launch_spmv_pq(v, mixed, k, false, s); }, 2 * k));
+            HIP_TRY(timed(h, kKUpdate, s, [&] { return launch_update(v, k, s); }, 2 * k));
             bool replaced = false;
             if (mixed && k % opt.replace_every == 0) {
-                HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidReplace, v.r, s); }));
+                HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidReplace, v.r, s); }, 2 * k));
                 replaced = true;
             }
             HIP_TRY(apply_iter(h, v, mixed, k, replaced, s));
         }
+        // a last iteration by recurrence leaves its decision to the next
+        // coarse launch: at max_iter, take it here
+        if (k == opt.max_iter && k > 0 && !direct(k))
+            HIP_TRY(launch_apply_coarse(v, mixed, kApplyIter, k, 0.0, false, mixed, false, s, true));
         return MAS_OK;
     };
     int inflight = 0, head = 0, next = 0;  // batch copies not yet looked at; ring slots 1 + (0|1)
@@ -465,7 +528,7 @@ int solve_impl(mas_handle* h, const mas_bcsr* H, const double* b, double* x, con
         // st.iter with it and go on
         k = st.iter;
         HIP_TRY(launch_clear_stop(v, s));
-        HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidConfirm, v.r, s); }));
+        HIP_TRY(timed(h, kKResidual, s, [&] { return launch_residual(v, kResidConfirm, v.r, s); }, 2 * k));
         HIP_TRY(apply_iter(h, v, mixed, k, true, s));
         if ((rc = read_state(h, v, s)) != MAS_OK) return rc;
         if (st.done || st.status < 0) break;
@@ -546,6 +609,16 @@ int analyze_impl(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row
     h->translated[1].resize(Q.dom_blk[0].size());
     for (size_t k = 0; k < Q.dom_blk[0].size(); ++k) h->translated[1][k] = Q.perm_src[Q.dom_blk[0][k]];
     make_layout(h);
+    const Plan& R = h->plan;
+    // three launches per iteration where the SpMV's restriction of q takes
+    // one pass of its threads (restrict_fast_ok): on systems whose groups
+    // have many more coarse units (a group of the membrane + bodies system
+    // has up to 448 writers), the longer restriction in the SpMV costs more
+    // than the x/r update launch it saves, and every iteration restricts r
+    // directly
+    h->fuse_ok = sizeof(double) * (3 * static_cast<size_t>(R.RG) + restrict_smem_doubles(R.RG, R.W1, R.L)) <=
+                     spmv_restrict_capacity() &&
+                 restrict_fast_ok(R.W1, R.GW, spmv_threads());
     return MAS_OK;
 }
 

@@ -42,10 +42,38 @@ __host__ __device__ inline int xcd_group(int b, int G) {
 
 // ---------------------------------------------------------------- reductions
 
+// x + x of the lane the DPP control selects (kCtrl: a permutation within
+// each row of 16 lanes, so every source lane exists); FP64 moved as two
+// 32-bit halves.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_add(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), kCtrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), kCtrl, 0xf, 0xf, false);
+    return x + __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double x, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), lane),
+                            __builtin_amdgcn_readlane(__double2loint(x), lane));
+}
+
+// row16_sum: the sum over each row of 16 lanes (every lane active) in all
+// of its lanes; wave_sum: over the 64 lanes of a wave, the same bits in
+// every lane.  Within each row of 16 lanes, partners at distance 1 and 2 (quad
+// permutations), then mirrored within each half row and within the row (at
+// each step both partners hold equal values, so a + b and b + a agree), then
+// the four row sums read out of lanes 0, 16, 32, 48 and added in a fixed
+// order.  DPP and readlane instead of shuffles through the LDS crossbar.
+__device__ inline double row16_sum(double v) {
+    v = dpp_add<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141>(v);  // row_half_mirror
+    return dpp_add<0x140>(v);  // row_mirror
+}
+
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v = row16_sum(v);
+    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
 }
 
 // Deterministic sum over the workgroup (whole waves only); the result is
@@ -77,6 +105,25 @@ __device__ inline double block_sum_last(double v, double* scratch) {
     if (threadIdx.x == 0)
         for (int w = 0; w < (blockDim.x >> 6); ++w) t += scratch[w];
     return t;
+}
+
+// Two block_sum_last reductions at once (same bits as two separate ones):
+// the results in thread 0 only; scratch: 2 * blockDim.x / 64 doubles.
+__device__ inline void block_sum2_last(double a, double b, double* scratch, double& sa, double& sb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        scratch[wave] = a;
+        scratch[nw + wave] = b;
+    }
+    __syncthreads();
+    sa = sb = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) {
+            sa += scratch[w];
+            sb += scratch[nw + w];
+        }
 }
 
 // Sum of n per-group partials in a fixed order that does not depend on the

@@ -63,6 +63,17 @@ struct SolverView {
     const int* gpos;              // its partial position, -1 if it writes none
     const uint64_t* gmask;        // writers: group-local level-1 units below it
     const uint64_t* lmask;        // [NS] leader slots: lanes of the domain in the slot's level-1 unit
+    // the restriction by output, padded per group: level-1 unit i of group g
+    // at [g * W1 + i] (lowest slot, -1 pad; lane mask), writer e of levels
+    // >= 2 at [g * GW + e] (partial position, -1 pad; entry (l - 2) W1 + i of
+    // the group's ganc row; member mask over the group's level-1 units)
+    const int* gu1_slot;
+    const uint64_t* gu1_mask;
+    int GW;
+    int rfast;  // restrict_fast_ok for the group kernels' block sizes (256 and 384 threads)
+    const int* gw_pos;
+    const int* gw_li;
+    const uint64_t* gw_mask;
     const int* cp_ptr[kMaxLv];    // l >= 2: [S_l + 1]
     // stored slot-ordered matrix (9 planes: H64 of nsb, H32 of nnzb values)
     double* H64;
@@ -77,6 +88,12 @@ struct SolverView {
     double* r1;
     double* y[kMaxLv];
     double* cpart;
+    // the same restrictions of q = H p (q1, qpart), and the restricted
+    // residual C_l r of levels l >= 2 ([3*ndom[l]*N]) that the coarse apply
+    // keeps between iterations: C_l r_k = C_l r_{k-1} - alpha_k C_l q_k
+    double* q1;
+    double* qpart;
+    double* rc[kMaxLv];
     // per-group partial sums [G] each
     double *P_sigma, *P_rr, *P_bb, *P_rho[2];
     DevState* st;
@@ -118,14 +135,30 @@ enum ResidMode {
     kResidConfirm = 2,  // as kResidReplace, run after the host cleared a stop
     kResidFinal = 3     // scratch = b - H x with ||.||^2 only
 };
-// Level-0 apply modes.
-enum ApplyMode { kApplyPlain = 0, kApplyInit = 1, kApplyIter = 2 };
+// MAS apply modes.
+//  kApplyPlain: z = M^-1 r outside PCG (no decision, no partials).
+//  kApplyInit:  the first apply of a solve; decision on r_0 with ||b||.
+//  kApplyIter:  iteration k after the x/r update kernel restricted r_k:
+//               coarse residuals straight from that restriction (kept for
+//               the recurrence), decision on r_k.
+//  kApplyRec:   iteration k without the x/r update kernel: the coarse launch
+//               forms alpha_k and C_l r_k = C_l r_{k-1} - alpha_k C_l q_k from
+//               the restriction of q_k the SpMV left, and takes the decision
+//               on r_{k-1}; the level-0 launch performs x += alpha p,
+//               r -= alpha q itself and leaves the ||r_k||^2 partials.
+enum ApplyMode { kApplyPlain = 0, kApplyInit = 1, kApplyIter = 2, kApplyRec = 3 };
 
 // spmv.hip
 hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void* val, bool f32, const double* x,
                             double* y, hipStream_t s);
-// iteration k: p_k = z_{k-1} + beta p_{k-1} (p_1 = z_0) into p[k & 1], q = H p_k, sigma partials
-hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s);
+// iteration k: p_k = z_{k-1} + beta p_{k-1} (p_1 = z_0) into p[k & 1], q = H p_k, sigma partials;
+// restrict_q: also the restriction of q to the coarse levels (q1, qpart)
+hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, bool restrict_q, hipStream_t s);
+// Bytes of shared memory the SpMV kernels can lend to the restriction of q
+// after their stream (their product planes).
+size_t spmv_restrict_capacity();
+// Threads per workgroup of the SpMV kernels.
+int spmv_threads();
 hipError_t launch_residual(const SolverView& v, int mode, double* out, hipStream_t s);
 
 // vectors.hip
@@ -144,11 +177,12 @@ hipError_t launch_adjoint_scatter(int n_rows, const int* rp, const int* ci, cons
 // mas.hip
 hipError_t launch_coarse_sums(const BuildView& b, const double* Hu, hipStream_t s);
 hipError_t launch_invert(const BuildView& b, const double* Hu, bool want32, hipStream_t s);
-// Coarse levels plus the convergence decision of iteration k (k = 0: the
-// initial apply); rr_true: the residual partials hold b - H x rather than the
-// recurrence (residual replacement, FP64 confirmation).
+// Coarse levels plus the convergence decision (mode as ApplyMode; k = 0:
+// the initial apply); rr_true: the residual partials hold b - H x rather
+// than the recurrence (residual replacement, FP64 confirmation).
+// decision_only: workgroup 0 alone (the decision on r_k, mode kApplyIter).
 hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, int k, double tol, bool x0_given, bool mixed,
-                               bool rr_true, hipStream_t s);
+                               bool rr_true, hipStream_t s, bool decision_only = false);
 hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, hipStream_t s);
 
 // assemble.hip: block-list assembly (scratch in the caller's workspace).

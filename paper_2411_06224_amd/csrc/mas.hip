@@ -317,18 +317,23 @@ __device__ void convergence_decision(const SolverView& v, int mode, int k, doubl
 }
 
 // Coarse levels l >= 1 (workgroups 1.. of the launch, one per domain, all
-// levels at once): r_l for the domain's N units -- level 1 straight from
-// r_1, higher levels as sums of the per-group partials the restriction left
-// for each unit (a contiguous range per unit; for N = 16 sixteen lanes per
-// unit, all units at once, else one wave per unit) -- then
-// y_l = Inv_{l,d} r_l.
+// levels at once): r_l for the domain's N units, then y_l = Inv_{l,d} r_l.
+// Straight from the residual's restriction (kApplyInit, kApplyIter,
+// kApplyPlain): level 1 from r_1, higher levels as sums of the per-group
+// partials the restriction left for each unit (a contiguous range per unit;
+// for N = 16 sixteen lanes per unit, all units at once, else one wave per
+// unit); levels >= 2 keep that r_l in rc_l.  By recurrence (kApplyRec,
+// iteration k): alpha_k = rho_{k-1} / sigma_k from the partials, and
+// r_l <- r_l - alpha_k (C_l q_k) with C_l q_k gathered in the same way from
+// the restriction of q_k the SpMV left (q_1, qpart); the unit's r_l (r_1 or
+// rc_l) is updated in place, each unit by the one workgroup of its domain.
 template <typename TI, int kN>
 __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab, int mode, int k, double tol,
                                                       int flags) {
     __shared__ double rl[128];
     __shared__ double buf[256];
     if (blockIdx.x == 0) {
-        if (mode != kApplyPlain) convergence_decision(v, mode, k, tol, flags, buf);
+        if (mode != kApplyPlain) convergence_decision(v, mode, mode == kApplyRec ? k - 1 : k, tol, flags, buf);
         return;
     }
     const int gb = blockIdx.x - 1;
@@ -339,6 +344,7 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
     const int u0 = d * N;
     const int nu = min(N, v.units[l] - u0);
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const bool rec = mode == kApplyRec;
     const TI* inv;
     if constexpr (sizeof(TI) == 8)
         inv = v.inv64[l];
@@ -360,17 +366,56 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
             }
         }
     }
-    // the stop flag is read once the inverse loads are in flight; after a
-    // stop nothing is written
+    // recurrence: the sigma partials and the unit's previous r_l, issued
+    // with the inverse loads (N = 16: lane 0 of each unit's 16-lane segment
+    // holds the unit's three components; level 1: thread t < 3 nu holds
+    // entry t of the domain's r_1 and q_1)
+    PartialLoads sig{};
+    double rho = 0.0, prev0 = 0.0, prev1 = 0.0, prev2 = 0.0, q1v = 0.0;
+    if (rec) {
+        sig = partials_load(v.P_sigma, v.G);
+        rho = v.st->rho[(k - 1) & 1];
+        if (l == 1) {
+            const int e = 3 * u0 + min(t, 3 * nu - 1);
+            prev0 = v.r1[e];
+            q1v = v.q1[e];
+        } else if (kN == 16) {
+            const int e = 3 * (u0 + min(t >> 4, nu - 1));
+            prev0 = v.rc[l][e];
+            prev1 = v.rc[l][e + 1];
+            prev2 = v.rc[l][e + 2];
+        }
+    }
+    // the stop flag is read once these loads are in flight; after a stop
+    // nothing is written
     const int stop = v.st->done;
     keep_loads_issued();
-    if (mode == kApplyIter && stop) return;
+    if ((mode == kApplyIter || rec) && stop) return;
+    double alpha = 0.0;
+    if (rec) {
+        const double sigma = partials_sum(sig, v.P_sigma, v.G, buf);
+        if (!(sigma > 0.0) || !finite(sigma) || !finite(rho)) return;  // the level-0 launch reports it
+        alpha = rho / sigma;
+    }
+    const bool keep = mode != kApplyPlain;  // r_l of levels >= 2 kept for the recurrence
     if (l == 1) {
-        if (t < n) rl[t] = t < 3 * nu ? v.r1[3 * u0 + t] : 0.0;
+        if (t < n) {
+            double val = 0.0;
+            if (t < 3 * nu) {
+                if (rec) {
+                    val = prev0 - alpha * q1v;
+                    v.r1[3 * u0 + t] = val;
+                } else {
+                    val = v.r1[3 * u0 + t];
+                }
+            }
+            rl[t] = val;
+        }
     } else if constexpr (kN == 16) {
         // all 16 units at once: 16 lanes per unit stride over its partials,
         // then fold within the 16-lane segment
         const int* cp = v.cp_ptr[l];
+        const double* part = rec ? v.qpart : v.cpart;
         const int a = t >> 4, sub = t & 15;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         if (a < nu) {
@@ -383,9 +428,9 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
                 double a0[kRound], a1[kRound], a2[kRound];
 #pragma unroll
                 for (int j = 0; j < kRound; ++j) {
-                    a0[j] = v.cpart[3 * (m + 16 * j)];
-                    a1[j] = v.cpart[3 * (m + 16 * j) + 1];
-                    a2[j] = v.cpart[3 * (m + 16 * j) + 2];
+                    a0[j] = part[3 * (m + 16 * j)];
+                    a1[j] = part[3 * (m + 16 * j) + 1];
+                    a2[j] = part[3 * (m + 16 * j) + 2];
                 }
 #pragma unroll
                 for (int j = 0; j < kRound; ++j) {
@@ -395,37 +440,46 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
                 }
             }
             for (; m < m1; m += 16) {
-                s0 += v.cpart[3 * m];
-                s1 += v.cpart[3 * m + 1];
-                s2 += v.cpart[3 * m + 2];
+                s0 += part[3 * m];
+                s1 += part[3 * m + 1];
+                s2 += part[3 * m + 2];
             }
         }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-            s0 += __shfl_xor(s0, o, 16);
-            s1 += __shfl_xor(s1, o, 16);
-            s2 += __shfl_xor(s2, o, 16);
-        }
+        s0 = row16_sum(s0);  // a unit's 16 lanes are one DPP row of the wave
+        s1 = row16_sum(s1);
+        s2 = row16_sum(s2);
         if (sub == 0) {
+            if (rec && a < nu) {
+                s0 = prev0 - alpha * s0;
+                s1 = prev1 - alpha * s1;
+                s2 = prev2 - alpha * s2;
+            }
+            if (keep && a < nu) {
+                double* rc = v.rc[l] + 3 * (u0 + a);
+                rc[0] = s0;
+                rc[1] = s1;
+                rc[2] = s2;
+            }
             rl[3 * a] = s0;
             rl[3 * a + 1] = s1;
             rl[3 * a + 2] = s2;
         }
     } else {
         const int* cp = v.cp_ptr[l];
+        const double* part = rec ? v.qpart : v.cpart;
         for (int a = w; a < N; a += 4) {
             double s0 = 0.0, s1 = 0.0, s2 = 0.0;
             if (a < nu) {
                 const int m0 = cp[u0 + a], m1 = cp[u0 + a + 1];
                 for (int m = m0 + lane; m < m1; m += 128) {
                     const int mb = m + 64;  // two independent loads in flight per lane
-                    s0 += v.cpart[3 * m];
-                    s1 += v.cpart[3 * m + 1];
-                    s2 += v.cpart[3 * m + 2];
+                    s0 += part[3 * m];
+                    s1 += part[3 * m + 1];
+                    s2 += part[3 * m + 2];
                     if (mb < m1) {
-                        s0 += v.cpart[3 * mb];
-                        s1 += v.cpart[3 * mb + 1];
-                        s2 += v.cpart[3 * mb + 2];
+                        s0 += part[3 * mb];
+                        s1 += part[3 * mb + 1];
+                        s2 += part[3 * mb + 2];
                     }
                 }
             }
@@ -433,6 +487,19 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
             s1 = wave_sum(s1);
             s2 = wave_sum(s2);
             if (lane == 0) {
+                if (a < nu) {
+                    double* rc = v.rc[l] + 3 * (u0 + a);
+                    if (rec) {
+                        s0 = rc[0] - alpha * s0;
+                        s1 = rc[1] - alpha * s1;
+                        s2 = rc[2] - alpha * s2;
+                    }
+                    if (keep) {
+                        rc[0] = s0;
+                        rc[1] = s1;
+                        rc[2] = s2;
+                    }
+                }
                 rl[3 * a] = s0;
                 rl[3 * a + 1] = s1;
                 rl[3 * a + 2] = s2;
@@ -463,14 +530,62 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
 
 constexpr int kPreLevels = 8;  // coarse levels whose corrections are prefetched
 
+// The x/r update of iteration k fused into the level-0 apply (kApplyRec):
+// alpha_k = rho_{k-1} / sigma_k from the partials, x += alpha p_k and
+// r -= alpha q_k on the thread's DOF (one per thread, slots of the group;
+// the vectors are padded to whole groups).  The loads are issued by
+// fused_load with the kernel's other early loads; fused_update returns
+// false, after flagging NOT_SPD (or NOT_FINITE) from group 0, when
+// sigma <= 0 or a value is not finite: every workgroup sees the same sigma
+// and returns without writing.  buf: 256 doubles of shared memory.
+struct FusedLoads {
+    PartialLoads sig;
+    double rho, x, p, r, q;
+};
+
+__device__ __forceinline__ FusedLoads fused_load(const SolverView& v, int k, long long i) {
+    FusedLoads F;
+    F.sig = partials_load(v.P_sigma, v.G);
+    F.rho = v.st->rho[(k - 1) & 1];
+    F.x = v.x[i];
+    F.p = v.p[k & 1][i];
+    F.r = v.r[i];
+    F.q = v.q[i];
+    return F;
+}
+
+__device__ __forceinline__ bool fused_update(const SolverView& v, int k, int g, long long i, bool live,
+                                             const FusedLoads& F, double* buf, double& rv) {
+    const double sigma = partials_sum(F.sig, v.P_sigma, v.G, buf);
+    if (!(sigma > 0.0) || !finite(sigma) || !finite(F.rho)) {
+        if (g == 0 && threadIdx.x == 0) {
+            v.st->status = (finite(sigma) && finite(F.rho)) ? -2 : -6;
+            v.st->done = 1;
+            v.st->iter = k - 1;
+        }
+        return false;
+    }
+    const double alpha = F.rho / sigma;
+    rv = 0.0;
+    if (live) {
+        v.x[i] = F.x + alpha * F.p;
+        rv = F.r - alpha * F.q;
+        v.r[i] = rv;
+    }
+    return true;
+}
+
 // Level 0 over a group of D0 domains, one thread per DOF:
 //   z = Inv_{0,d} r_d + sum_{l >= 1} y_l[unit of the slot at level l]
 // (prolongation of every coarse level, Supp. Eq. 6) and the partial of
-// rho = r^T z.  Returns at once after a stop.
+// rho = r^T z; kApplyRec first performs the x/r update of iteration k and
+// also leaves the partial of ||r_k||^2.  Returns at once after a stop.
 template <typename TI, int kN, int kMode>
 __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
+    constexpr bool kFused = kMode == kApplyRec;
     __shared__ double rs[384];
-    __shared__ double red[8];
+    __shared__ double red[16];
+    __shared__ double pbuf[kFused ? 256 : 1];
     const int N = kN > 0 ? kN : v.N;
     const int n = 3 * N;
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
@@ -484,12 +599,20 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
 #pragma unroll
     for (int j = 0; j < kPreLevels; ++j)
         u[j] = (live && j + 1 < v.L) ? v.anc[static_cast<long long>(j) * v.NS + slot] : -1;
-    const double rv = live ? v.r[base + t] : 0.0;
+    FusedLoads F{};
+    double rv = 0.0;
+    if constexpr (kFused)
+        F = fused_load(v, k, base + t);
+    else
+        rv = live ? v.r[base + t] : 0.0;
     // the stop flag is read once these loads are in flight; after a stop
     // nothing is written
     const int stop = v.st->done;
     keep_loads_issued();
     if (kMode != kApplyPlain && stop) return;
+    if constexpr (kFused) {
+        if (!fused_update(v, k, g, base + t, live, F, pbuf, rv)) return;
+    }
     double ycor[kPreLevels];
 #pragma unroll
     for (int j = 0; j < kPreLevels; ++j) ycor[j] = u[j] >= 0 ? v.y[j + 1][3 * u[j] + c] : 0.0;
@@ -536,8 +659,17 @@ __global__ void __launch_bounds__(384) k_apply_level0(SolverView v, int k) {
         v.z[base + t] = zv;
     }
     if (kMode == kApplyPlain) return;
-    const double part = block_sum_last(rv * zv, red);
-    if (t == 0) v.P_rho[k & 1][g] = part;
+    if constexpr (kFused) {
+        double prho, prr;
+        block_sum2_last(rv * zv, rv * rv, red, prho, prr);
+        if (t == 0) {
+            v.P_rho[k & 1][g] = prho;
+            v.P_rr[g] = prr;
+        }
+    } else {
+        const double part = block_sum_last(rv * zv, red);
+        if (t == 0) v.P_rho[k & 1][g] = part;
+    }
 }
 
 // Level 0 with the symmetric-packed FP64 inverses (domain size 16), over a
@@ -556,10 +688,11 @@ constexpr int kStageLoads = (kPairs * kPacked + 383) / 384;  // entries per thre
 
 template <typename TI, int kMode>
 __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k) {
+    constexpr bool kFused = kMode == kApplyRec;
     __shared__ double rs[384];
     __shared__ double zs[384];
     __shared__ TI stage[kPairs * kPacked];
-    __shared__ double red[8];
+    __shared__ double red[16];
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
     const int nd = min(v.D0, v.M - g * v.D0);  // domains of this group
     const bool live = t < nd * 48;
@@ -584,12 +717,21 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
         }
     };
     fetch(0);
-    const double rv = live ? v.r[base + t] : 0.0;
+    FusedLoads F{};
+    double rv = 0.0;
+    if constexpr (kFused)
+        F = fused_load(v, k, base + t);
+    else
+        rv = live ? v.r[base + t] : 0.0;
     // the stop flag is read once these loads are in flight; after a stop
     // nothing is written
     const int stop = v.st->done;
     keep_loads_issued();
     if (kMode != kApplyPlain && stop) return;
+    if constexpr (kFused) {
+        // zs is first written after the first round's barrier
+        if (!fused_update(v, k, g, base + t, live, F, zs, rv)) return;
+    }
     if (t < 384) rs[t] = rv;
     const int row = t >> 2, q = t & 3;  // 96 rows of a pair, four quarters each
     const int dl = row / 48, i = row - 48 * dl;
@@ -615,8 +757,8 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
             }
         }
         // the row's four quarters, added as (q0 + q1) + (q2 + q3)
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
+        s = dpp_add<0xb1>(s);  // quad_perm [1, 0, 3, 2]
+        s = dpp_add<0x4e>(s);  // quad_perm [2, 3, 0, 1]
         if (q == 0 && d < nd) zs[48 * d + i] = s;
         __syncthreads();  // stage free for the next pair
     }
@@ -640,8 +782,17 @@ __global__ void __launch_bounds__(384) k_apply_level0_packed(SolverView v, int k
         v.z[base + t] = zv;
     }
     if (kMode == kApplyPlain) return;
-    const double part = block_sum_last(rv * zv, red);
-    if (t == 0) v.P_rho[k & 1][g] = part;
+    if constexpr (kFused) {
+        double prho, prr;
+        block_sum2_last(rv * zv, rv * rv, red, prho, prr);
+        if (t == 0) {
+            v.P_rho[k & 1][g] = prho;
+            v.P_rr[g] = prr;
+        }
+    } else {
+        const double part = block_sum_last(rv * zv, red);
+        if (t == 0) v.P_rho[k & 1][g] = part;
+    }
 }
 
 DomTable make_table(const int* ndom, int first, int L) {
@@ -698,9 +849,9 @@ hipError_t launch_invert(const BuildView& b, const double* Hu, bool want32, hipS
 }
 
 hipError_t launch_apply_coarse(const SolverView& v, bool f32, int mode, int k, double tol, bool x0_given, bool mixed,
-                               bool rr_true, hipStream_t s) {
+                               bool rr_true, hipStream_t s, bool decision_only) {
     const DomTable tab = make_table(v.ndom, 1, v.L);
-    const int total = 1 + tab.off[kMaxLv];  // workgroup 0 decides convergence
+    const int total = decision_only ? 1 : 1 + tab.off[kMaxLv];  // workgroup 0 decides convergence
     const int flags = (x0_given ? kFlagX0 : 0) | (mixed ? kFlagMixed : 0) | (rr_true ? kFlagRrTrue : 0);
     if (v.N == 16) {
         if (f32) launch_kernel((k_apply_coarse<float, 16>), dim3(total), dim3(256), 0, s, v, tab, mode, k, tol, flags);
@@ -720,16 +871,20 @@ void launch_level0_t(const SolverView& v, int mode, int k, hipStream_t s) {
             launch_kernel((k_apply_level0_packed<TI, kApplyPlain>), g, b, 0, s, v, k);
         else if (mode == kApplyInit)
             launch_kernel((k_apply_level0_packed<TI, kApplyInit>), g, b, 0, s, v, k);
-        else
+        else if (mode == kApplyIter)
             launch_kernel((k_apply_level0_packed<TI, kApplyIter>), g, b, 0, s, v, k);
+        else
+            launch_kernel((k_apply_level0_packed<TI, kApplyRec>), g, b, 0, s, v, k);
         return;
     }
     if (mode == kApplyPlain)
         launch_kernel((k_apply_level0<TI, kN, kApplyPlain>), g, b, 0, s, v, k);
     else if (mode == kApplyInit)
         launch_kernel((k_apply_level0<TI, kN, kApplyInit>), g, b, 0, s, v, k);
-    else
+    else if (mode == kApplyIter)
         launch_kernel((k_apply_level0<TI, kN, kApplyIter>), g, b, 0, s, v, k);
+    else
+        launch_kernel((k_apply_level0<TI, kN, kApplyRec>), g, b, 0, s, v, k);
 }
 
 hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, hipStream_t s) {

@@ -561,6 +561,41 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
             }
     }
 
+    // the restriction tables by output (see Plan)
+    P.gu1_slot.assign(static_cast<size_t>(P.G) * P.W1, -1);
+    P.gu1_mask.assign(static_cast<size_t>(P.G) * P.W1, 0);
+    if (P.L > 1)
+        for (int s = 0; s < P.NS; ++s) {
+            const int u = P.lead1[s];
+            if (u < 0) continue;
+            const int g = s / P.RG;
+            const size_t o = static_cast<size_t>(g) * P.W1 + (u - P.g_u1[g]);
+            P.gu1_slot[o] = s;
+            P.gu1_mask[o] = P.lmask[s];
+        }
+    P.GW = 1;
+    std::vector<std::vector<std::array<long long, 3>>> writers(P.G);
+    for (int l = 2; l < P.L; ++l)
+        for (int g = 0; g < P.G; ++g)
+            for (int i = 0; i < P.W1; ++i) {
+                const size_t o = static_cast<size_t>(g) * P.W1 + i;
+                if (P.gpos[l][o] < 0) continue;
+                writers[g].push_back({P.gpos[l][o], static_cast<long long>(l - 2) * P.W1 + i,
+                                      static_cast<long long>(o)});
+            }
+    for (int g = 0; g < P.G; ++g) P.GW = std::max(P.GW, static_cast<int>(writers[g].size()));
+    P.gw_pos.assign(static_cast<size_t>(P.G) * P.GW, -1);
+    P.gw_li.assign(static_cast<size_t>(P.G) * P.GW, 0);
+    P.gw_mask.assign(static_cast<size_t>(P.G) * P.GW, 0);
+    for (int g = 0; g < P.G; ++g)
+        for (size_t e = 0; e < writers[g].size(); ++e) {
+            const size_t o = static_cast<size_t>(g) * P.GW + e;
+            P.gw_pos[o] = static_cast<int>(writers[g][e][0]);
+            P.gw_li[o] = static_cast<int>(writers[g][e][1]);
+            const int l = 2 + static_cast<int>(writers[g][e][1] / P.W1);
+            P.gw_mask[o] = P.gmask[l][static_cast<size_t>(writers[g][e][2])];
+        }
+
     symmetric_storage(P);
     spmv_order(P);
 

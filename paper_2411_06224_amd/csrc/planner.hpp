@@ -76,6 +76,17 @@ struct Plan {
     // Used when W1 <= 64.
     std::vector<uint64_t> lmask;
     std::vector<std::vector<uint64_t>> gmask;
+    // The same restriction by output, padded per group so that thread t of a
+    // group's workgroup finds its entry at a fixed place: level-1 unit i of
+    // group g at [g * W1 + i]: its lowest slot (-1 pad) and lane mask; the
+    // writers of levels >= 2 at [g * GW + e] (GW = the most writers of one
+    // group): partial position (-1 pad), entry (l - 2) * W1 + i of the
+    // group's ganc / gpos row, and member mask (W1 <= 64).
+    std::vector<int> gu1_slot;
+    std::vector<uint64_t> gu1_mask;
+    int GW = 1;
+    std::vector<int> gw_pos, gw_li;
+    std::vector<uint64_t> gw_mask;
     // Prolongation: unit of every slot at levels 1..L-1, [(l-1) * NS + slot], -1 = empty.
     std::vector<int> anc;
 

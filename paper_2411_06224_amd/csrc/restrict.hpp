@@ -1,44 +1,27 @@
-// Restriction of a residual to the coarse levels (C_l r of Supp. Eq. 6),
-// computed by the workgroup that owns a group of level-0 domains.
+// Restriction of a residual (or of q = H p) to the coarse levels (C_l r of
+// Supp. Eq. 6), computed by the workgroup that owns a group of level-0
+// domains.
 //
 // restrict_load() issues every plan load of the group at once into
-// registers, and restrict_stage() writes them to shared memory later, just
-// before the barrier that publishes the residual: the loads' latency overlaps
-// whatever the kernel does in between, and no wait for them sits on the
-// kernel's early path.  restrict_group() then works from shared memory only.
+// registers, early in a kernel, so that no wait for them sits on the
+// kernel's path; restrict_group() then works from those registers and the
+// vector staged in shared memory.  Each sum reads its terms from shared
+// memory as independent loads, several at a time, and adds them in
+// ascending order, non-members as +0.0 (which leaves every partial sum's
+// bits unchanged: a sum that starts at +0.0 never becomes -0.0), so the
+// result is the member-only sum in lane order.
 #pragma once
 
 #include "launch.hpp"
 
 namespace maspcg {
 
-// Shared memory of the restriction, in doubles, for a group of RG slots with
-// at most W1 level-1 units and L levels: r1s[3 W1] doubles, lmask[RG] and
-// gmask[(L-2) W1] 64-bit masks, then up0[RG], lead[RG], anc[(L-2) W1],
-// pos[(L-2) W1] ints.
+// Shared memory of the restriction, in doubles, for a group with at most W1
+// level-1 units: the group's level-1 sums r1s[3 W1].
 __host__ __device__ inline int restrict_smem_doubles(int RG, int W1, int L) {
-    const int lv = L > 2 ? L - 2 : 0;
-    const int ints = 2 * RG + 2 * lv * W1;
-    return 3 * W1 + RG + lv * W1 + (ints + 1) / 2;
-}
-
-struct RestrictSmem {
-    double* r1s;
-    uint64_t *lmask, *gmask;
-    int *up0, *lead, *anc, *pos;
-};
-
-__device__ inline RestrictSmem restrict_layout(const SolverView& v, double* sm) {
-    const int lv = v.L > 2 ? v.L - 2 : 0;
-    RestrictSmem r;
-    r.r1s = sm;
-    r.lmask = reinterpret_cast<uint64_t*>(sm + 3 * v.W1);
-    r.gmask = r.lmask + v.RG;
-    r.up0 = reinterpret_cast<int*>(r.gmask + lv * v.W1);
-    r.lead = r.up0 + v.RG;
-    r.anc = r.lead + v.RG;
-    r.pos = r.anc + lv * v.W1;
-    return r;
+    (void)RG;
+    (void)L;
+    return 3 * W1;
 }
 
 // The group's range of level-1 units: first unit and count.
@@ -46,131 +29,139 @@ struct GroupUnits {
     int lo, n;
 };
 
-// Plan entries a thread holds in registers between restrict_load and
-// restrict_stage: its slot's entries and kPlanRegs entries of the group's
-// level >= 2 table; a larger table's remainder is loaded by restrict_stage.
-constexpr int kPlanRegs = 1;
-
+// Plan entries a thread holds in registers: thread t takes component t % 3
+// of the group's level-1 unit t / 3 and of its level >= 2 writer t / 3
+// (the common case, restrict_fast_ok; else the entries are loaded where
+// they are used).
 struct RestrictLoads {
     GroupUnits gu;
-    int up0, lead;  // raw loads at clamped indices: restrict_stage drops the
-    uint64_t lmask; // ones outside the group's slots and table row
-    int anc[kPlanRegs], pos[kPlanRegs];
-    uint64_t gm[kPlanRegs];
+    int u1_slot;      // lowest slot of the thread's level-1 unit (-1 pad)
+    uint64_t u1_mask; // lanes of its domain in that unit
+    int w_pos, w_li;  // the thread's writer: partial position (-1 pad), table entry
+    uint64_t w_mask;  // the writer's members among the group's level-1 units
 };
 
-// Issues the loads of the group's plan: level-1 unit, writer flag and member
-// mask of every slot, and for every level l >= 2 the ancestor, writer
-// position and writer mask of every level-1 unit of the group (entry
-// (l - 2) W1 + i of the group's row of the level-major tables, so that the
-// whole row is one coalesced range and no load waits for another).  One
-// slot per thread: RG = D0 N <= 128 and every kernel that restricts runs at
-// least 256 threads.  The loads are issued unconditionally, at clamped
-// indices (arrays of NS entries stand in for tables a shallow hierarchy does
-// not have), so that no branch separates them from the loads issued before
-// them and a wait for those need not wait for these too.
+// Issues the loads of the group's plan, all at once and unconditionally (at
+// clamped indices), so that no branch separates them from the loads issued
+// before them and a wait for those need not wait for these too.
 __device__ inline RestrictLoads restrict_load(const SolverView& v, int g) {
     RestrictLoads R;
     const int t = threadIdx.x;
-    const bool lv1 = v.L >= 2, lv2 = v.L > 2;
     const int u1_lo = v.g_u1[g];
-    R.gu = lv1 ? GroupUnits{u1_lo, v.g_u1[g + 1] - u1_lo} : GroupUnits{0, 0};
-    const int sc = min(g * v.RG + t, v.NS - 1);
-    R.up0 = (lv1 ? v.anc : v.lead1)[sc];
-    R.lead = v.lead1[sc];
-    R.lmask = v.lmask[sc];
-    const int tot = lv2 ? (v.L - 2) * v.W1 : 0;
-    const long long row = static_cast<long long>(g) * tot;
-    const long long last = lv2 ? static_cast<long long>(v.G) * tot - 1 : 0;
-#pragma unroll
-    for (int j = 0; j < kPlanRegs; ++j) {
-        const long long e = min(row + t + j * static_cast<int>(blockDim.x), last);
-        R.anc[j] = (lv2 ? v.ganc : v.lead1)[e];
-        R.pos[j] = (lv2 ? v.gpos : v.lead1)[e];
-        R.gm[j] = (lv2 ? v.gmask : v.lmask)[e];
-    }
+    R.gu = v.L >= 2 ? GroupUnits{u1_lo, v.g_u1[g + 1] - u1_lo} : GroupUnits{0, 0};
+    const long long i1 = static_cast<long long>(g) * v.W1 + min(t / 3, v.W1 - 1);
+    R.u1_slot = v.gu1_slot[i1];
+    R.u1_mask = v.gu1_mask[i1];
+    const long long iw = static_cast<long long>(g) * v.GW + min(t / 3, v.GW - 1);
+    R.w_pos = v.gw_pos[iw];
+    R.w_li = v.gw_li[iw];
+    R.w_mask = v.gw_mask[iw];
     return R;
 }
 
-// Writes the loaded plan to shared memory (needs a barrier before
-// restrict_group) and returns the group's level-1 unit range.
-__device__ inline GroupUnits restrict_stage(const SolverView& v, int g, const RestrictLoads& R, double* sm) {
-    if (v.L < 2) return R.gu;
-    const RestrictSmem S = restrict_layout(v, sm);
-    const int t = threadIdx.x;
-    if (t < v.RG) {
-        const bool in = g * v.RG + t < v.NS;
-        S.up0[t] = in ? R.up0 : -1;
-        S.lead[t] = in ? R.lead : -1;
-        S.lmask[t] = in ? R.lmask : 0;
-    }
-    const int tot = (v.L - 2) * v.W1;
-#pragma unroll
-    for (int j = 0; j < kPlanRegs; ++j) {
-        const int o = t + j * static_cast<int>(blockDim.x);
-        if (o < tot) {
-            S.anc[o] = R.anc[j];
-            S.pos[o] = R.pos[j];
-            S.gmask[o] = R.gm[j];
-        }
-    }
-    const long long row = static_cast<long long>(g) * tot;
-    for (int o = t + kPlanRegs * static_cast<int>(blockDim.x); o < tot; o += blockDim.x) {
-        S.anc[o] = v.ganc[row + o];
-        S.pos[o] = v.gpos[row + o];
-        S.gmask[o] = v.gmask[row + o];
-    }
-    return R.gu;
+// Makes the plan registers ready now (their loads completed long before):
+// called before a kernel's last stores, so that using them afterwards waits
+// for nothing.  Loads and stores share one counter, and after a loop whose
+// loads the compiler cannot count, a first use of an early-loaded register
+// waits for every outstanding access -- the stores just issued included.
+__device__ __forceinline__ void restrict_ready(const RestrictLoads& R) {
+    asm volatile("" ::"v"(R.u1_slot), "v"(R.u1_mask), "v"(R.w_pos), "v"(R.w_li), "v"(R.w_mask));
 }
 
-// rs[3*RG]: the group's residual in slot order (zero on slots >= NS), and
-// the prefetched plan, both visible to the workgroup (barrier done by the
-// caller).  Writes r_1 for the level-1 supernodes of the group (each summed
-// by its lowest slot, lanes in ascending order) and, for every level l >= 2,
-// one partial sum per (group, level-l supernode) at the position the plan
-// assigns (summed over the group's level-1 supernodes below it, ascending).
-// No atomics: every output has exactly one writer.
-__device__ inline void restrict_group(const SolverView& v, GroupUnits gu, const double* rs, double* sm) {
+// sum over the members m < n of mask, in ascending m, of x[3 m] (x in shared
+// memory): eight independent loads per round, each round's members added as
+// a balanced tree (non-members as +0.0) and the round's sum to the total
+__device__ __forceinline__ double masked_sum_tree(const double* x, uint64_t mask, int n) {
+    double s = 0.0;
+    for (int m0 = 0; m0 < n; m0 += 8) {
+        double a[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const double e = x[3 * min(m0 + j, n - 1)];
+            a[j] = (m0 + j < n && ((mask >> (m0 + j)) & 1u)) ? e : 0.0;
+        }
+        s += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+    return s;
+}
+
+// rs[3*RG]: the group's vector in slot order (zero on slots >= NS), visible
+// to the workgroup (barrier done by the caller); R: restrict_load(v, g);
+// sm: restrict_smem_doubles of shared memory.  Writes out1 (level 1: the
+// residual r_1, or q_1 of q = H p) for the level-1 supernodes of the group
+// (lanes of the unit in ascending order) and, for every level l >= 2, one
+// partial sum per (group, level-l supernode) into outpart at the position
+// the plan assigns (the group's level-1 supernodes below it, ascending).
+// No atomics: every output has exactly one writer.  Contains a barrier when
+// L > 2 (every thread must call it).  kFast: the caller guarantees
+// GW <= blockDim.x and W1 <= 64 (restrict_fast_ok), and the restriction then
+// reads no global memory -- a load here would make the stores before it
+// wait too.
+__host__ __device__ inline bool restrict_fast_ok(int W1, int GW, int threads) {
+    return W1 <= 64 && 3 * W1 <= threads && 3 * GW <= threads;
+}
+
+template <bool kFast = false>
+__device__ inline void restrict_group(const SolverView& v, int g, const RestrictLoads& R, const double* rs,
+                                      double* sm, double* __restrict__ out1, double* __restrict__ outpart) {
     if (v.L < 2) return;
-    const RestrictSmem S = restrict_layout(v, sm);
-    const int RG = v.RG, N = v.N;
-    const int u1_lo = gu.lo, n1 = gu.n;
-    for (int o = threadIdx.x; o < 3 * RG; o += blockDim.x) {
-        const int ls = o / 3, c = o - 3 * ls;
-        const int u = S.lead[ls];
-        if (u < 0) continue;
-        const int first = (ls / N) * N;
-        double s = 0.0;
-        if (v.W1 <= 64) {
-            // the unit's lanes from the precomputed mask, ascending
-            for (uint64_t m = S.lmask[ls]; m; m &= m - 1) s += rs[3 * (first + __ffsll(static_cast<unsigned long long>(m)) - 1) + c];
-        } else {
-            for (int a = 0; a < N; ++a)
-                if (S.up0[first + a] == u) s += rs[3 * (first + a) + c];
+    const int t = threadIdx.x, N = v.N;
+    const int u1_lo = R.gu.lo, n1 = R.gu.n;
+    double* r1s = sm;
+    // one thread per (level-1 unit, component); passes after the first
+    // (not in the fast case) load their entries here
+    for (int o = t; o < 3 * n1; o += blockDim.x) {
+        const int i = o / 3, c = o - 3 * i;
+        int slot = R.u1_slot;
+        uint64_t m = R.u1_mask;
+        if (!kFast && o != t) {
+            slot = v.gu1_slot[static_cast<long long>(g) * v.W1 + i];
+            m = v.gu1_mask[static_cast<long long>(g) * v.W1 + i];
         }
-        v.r1[3 * u + c] = s;
-        S.r1s[3 * (u - u1_lo) + c] = s;
+        const int first = (slot - g * v.RG) / N * N;  // the unit's domain, local slots
+        const double s1 = masked_sum_tree(rs + 3 * first + c, m, N);
+        out1[3 * u1_lo + o] = s1;
+        r1s[o] = s1;
+        if (kFast) break;
     }
-    if (v.L > 2) {
-        __syncthreads();
-        const int tot = 3 * (v.L - 2) * n1;
-        for (int o = threadIdx.x; o < tot; o += blockDim.x) {
-            const int li = o / 3, c = o - 3 * li;
-            const int l = li / n1, i = li - l * n1;
-            const int pos = S.pos[l * v.W1 + i];
-            if (pos < 0) continue;
-            double s = 0.0;
-            if (v.W1 <= 64) {
-                for (uint64_t m = S.gmask[l * v.W1 + i]; m; m &= m - 1) s += S.r1s[3 * (__ffsll(static_cast<unsigned long long>(m)) - 1) + c];
-            } else {
-                const int* anc = S.anc + l * v.W1;
-                const int a = anc[i];
+    if (v.L <= 2) return;
+    __syncthreads();
+    // one thread per (writer of levels >= 2, component)
+    for (int o = t; o < 3 * v.GW; o += blockDim.x) {
+        const int e = o / 3, c = o - 3 * e;
+        int pos = R.w_pos, li = R.w_li;
+        uint64_t m = R.w_mask;
+        if (!kFast && o != t) {
+            const long long k = static_cast<long long>(g) * v.GW + e;
+            pos = v.gw_pos[k];
+            li = v.gw_li[k];
+            m = v.gw_mask[k];
+        }
+        if (pos >= 0) {
+            double s2;
+            if (kFast || v.W1 <= 64) {
+                s2 = masked_sum_tree(r1s + c, m, n1);
+            } else {  // more level-1 units in the group than mask bits: compare ancestors
+                const int* anc = v.ganc + static_cast<long long>(g) * (v.L - 2) * v.W1 + (li / v.W1) * v.W1;
+                const int a = anc[li % v.W1];
+                s2 = 0.0;
                 for (int j = 0; j < n1; ++j)
-                    if (anc[j] == a) s += S.r1s[3 * j + c];
+                    if (anc[j] == a) s2 += r1s[3 * j + c];
             }
-            v.cpart[3 * pos + c] = s;
+            outpart[3 * pos + c] = s2;
         }
+        if (kFast) break;
     }
+}
+
+// restrict_group with the fast path when the host found it applicable
+// (v.rfast: tables that fit blocks of 256 threads and more).
+__device__ inline void restrict_group_any(const SolverView& v, int g, const RestrictLoads& R, const double* rs,
+                                          double* sm, double* __restrict__ out1, double* __restrict__ outpart) {
+    if (v.rfast)
+        restrict_group<true>(v, g, R, rs, sm, out1, outpart);
+    else
+        restrict_group<false>(v, g, R, rs, sm, out1, outpart);
 }
 
 }  // namespace maspcg

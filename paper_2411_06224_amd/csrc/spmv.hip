@@ -308,6 +308,43 @@ __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* _
     }
 }
 
+// Products per launch after the stream: q of the group's rows, the partial
+// of p_k^T q and, with kRQ = 1, the restriction of q to
+// the coarse levels (q1 and qpart, as restrict_group computes C_l r) from
+// the plan pl loaded at the kernel's start, staged in the product planes
+// (free once the stream's last barrier has passed; the host checks that
+// they hold it, spmv_restrict_capacity).
+template <int kRQ>
+__device__ __forceinline__ void finish_pq(const SolverView& v, int g, int nown, int r0, const double (&acc)[2],
+                                          const double (&pv)[2], double* prod, double* buf, const RestrictLoads& pl) {
+    const int t = threadIdx.x;
+    if constexpr (kRQ) restrict_ready(pl);
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int o = t + q * kThreads;
+        if (o < nown) {
+            v.q[3LL * r0 + o] = acc[q];
+            part += pv[q] * acc[q];
+        }
+    }
+    if constexpr (kRQ) {
+        double* rs = prod;
+        double* rsm = prod + 3 * v.RG;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int o = t + q * kThreads;
+            if (o < 3 * v.RG) rs[o] = o < nown ? acc[q] : 0.0;
+        }
+        part = block_sum<false>(part, buf);  // its barriers also publish rs
+        if (t == 0) v.P_sigma[g] = part;
+        restrict_group<true>(v, g, pl, rs, rsm, v.q1, v.qpart);  // the host checked restrict_fast_ok
+    } else {
+        part = block_sum<false>(part, buf);  // the kernel's last use of buf
+        if (t == 0) v.P_sigma[g] = part;
+    }
+}
+
 // PCG iteration k over the solver's group of slots: the new direction
 // p_k = z_{k-1} + beta_{k-1} p_{k-1} (beta = rho_{k-1} / rho_{k-2} summed from
 // the group partials; p_1 = z_0) is formed first on the group's own slots
@@ -315,7 +352,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* _
 // it; q = H p_k and the partial of p_k^T q.  Every workgroup forms the same
 // beta and the same fused multiply-add, so a direction entry has the same
 // bits in every workgroup that reads it.
-template <typename T>
+template <typename T, int kRQ>
 __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __restrict__ H, int k) {
     __shared__ double prod[3 * kPlane];
     __shared__ double buf[256];
@@ -339,6 +376,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
         po[q] = pold[e];
     }
     const ChunkCols c0 = chunk_cols(v.ci0, v.rp0[r0], v.rp0[r1]);
+    RestrictLoads pl{};
+    if constexpr (kRQ) pl = restrict_load(v, g);
     const int stop = v.st->done;
     keep_loads_issued();
     if (stop) return;  // after a stop nothing is written
@@ -363,23 +402,13 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
     double acc[2];
     stream_rows<T, true, XDir, true>(v.rp0, v.ci0, Blocks<T, true>{H, v.nnzb}, XDir{v.z, pold, beta}, r0, r1, prod,
                                      acc, c0, xs);
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int o = t + q * kThreads;
-        if (o < nown) {
-            v.q[3LL * r0 + o] = acc[q];
-            part += pv[q] * acc[q];
-        }
-    }
-    part = block_sum<false>(part, buf);  // the kernel's last use of buf
-    if (t == 0) v.P_sigma[g] = part;
+    finish_pq<kRQ>(v, g, nown, r0, acc, pv, prod, buf, pl);
 }
 
 // k_spmv_pq on the group-symmetric storage: the group forms the new
 // direction on its own slots first (into LDS and p_k) and gathers it only for
 // columns outside the group.
-template <typename T>
+template <typename T, int kRQ>
 __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T* __restrict__ H, int k) {
     __shared__ double prod[6 * kSymPlane];
     __shared__ double buf[256];
@@ -411,6 +440,8 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
 #pragma unroll
     for (int j = 0; j < kTlRegs; ++j) tlr[j] = tsrc[min(t + j * kThreads, max(tn - 1, 0))];
     const SymCols c0 = sym_cols(v, v.srp[r0], v.srp[r1]);
+    RestrictLoads pl{};
+    if constexpr (kRQ) pl = restrict_load(v, g);
     const int stop = v.st->done;
     keep_loads_issued();
     if (stop) return;  // after a stop nothing is written
@@ -438,17 +469,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
     __syncthreads();
     double acc[2];
     stream_sym<T>(v, H, XDir{v.z, pold, beta}, xs, tl, tb0, r0, r1, prod, acc, c0);
-    double part = 0.0;
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int o = t + q * kThreads;
-        if (o < nown) {
-            v.q[3LL * r0 + o] = acc[q];
-            part += pv[q] * acc[q];
-        }
-    }
-    part = block_sum<false>(part, buf);  // the kernel's last use of buf
-    if (t == 0) v.P_sigma[g] = part;
+    finish_pq<kRQ>(v, g, nown, r0, acc, pv, prod, buf, pl);
 }
 
 // out = b - H x in FP64 over a group, with the partials of ||out||^2 (and
@@ -477,6 +498,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
         stream_rows<double, true>(v.rp0, v.ci0, Blocks<double, true>{v.H64, v.nnzb}, XVec{v.x}, r0, r1, prod, acc,
                                   chunk_cols(v.ci0, v.rp0[r0], v.rp0[r1]));
     }
+    restrict_ready(pl);
     double rr = 0.0, bb = 0.0;
     double* rs = dyn;
 #pragma unroll
@@ -495,14 +517,13 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
             rs[o] = e;
         }
     }
-    const GroupUnits gu = restrict_stage(v, g, pl, dyn + 3 * v.RG);
-    rr = block_sum(rr, scratch);  // its barriers also publish rs and the plan
+    rr = block_sum(rr, scratch);  // its barriers also publish rs
     if (kMode == kResidInit) bb = block_sum(bb, scratch);
     if (threadIdx.x == 0) {
         v.P_rr[g] = rr;
         if (kMode == kResidInit) v.P_bb[g] = bb;
     }
-    if (kMode != kResidFinal) restrict_group(v, gu, rs, dyn + 3 * v.RG);
+    if (kMode != kResidFinal) restrict_group_any(v, g, pl, rs, dyn + 3 * v.RG, v.r1, v.cpart);
 }
 
 }  // namespace
@@ -518,18 +539,32 @@ hipError_t launch_spmv_user(int n_rows, const int* rp, const int* ci, const void
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, hipStream_t s) {
+template <int kRQ>
+void launch_spmv_pq_t(const SolverView& v, bool f32, int k, hipStream_t s) {
     dim3 g(v.G), b(kThreads);
     if (v.sym && !f32) {
         const size_t shmem = sizeof(double) * 3 * v.RG + sizeof(int) * v.maxT;
-        launch_kernel(k_spmv_pq_sym<double>, g, b, shmem, s, v, static_cast<const double*>(v.H64), k);
+        launch_kernel(k_spmv_pq_sym<double, kRQ>, g, b, shmem, s, v, static_cast<const double*>(v.H64), k);
     } else if (f32) {
-        launch_kernel(k_spmv_pq<float>, g, b, 0, s, v, static_cast<const float*>(v.H32), k);
+        launch_kernel(k_spmv_pq<float, kRQ>, g, b, 0, s, v, static_cast<const float*>(v.H32), k);
     } else {
-        launch_kernel(k_spmv_pq<double>, g, b, 0, s, v, static_cast<const double*>(v.H64), k);
+        launch_kernel(k_spmv_pq<double, kRQ>, g, b, 0, s, v, static_cast<const double*>(v.H64), k);
     }
+}
+
+hipError_t launch_spmv_pq(const SolverView& v, bool f32, int k, bool restrict_q, hipStream_t s) {
+    if (!restrict_q)
+        launch_spmv_pq_t<0>(v, f32, k, s);
+    else if (v.rfast)
+        launch_spmv_pq_t<1>(v, f32, k, s);
+    else
+        return hipErrorInvalidValue;  // the solver restricts q in the SpMV only where restrict_fast_ok holds
     return hipGetLastError();
 }
+
+int spmv_threads() { return kThreads; }
+
+size_t spmv_restrict_capacity() { return sizeof(double) * static_cast<size_t>(min(3 * kPlane, 6 * kSymPlane)); }
 
 template <bool kSym>
 void launch_residual_t(const SolverView& v, int mode, double* out, hipStream_t s) {

@@ -91,18 +91,18 @@ __global__ void k_init_rhs(SolverView v) {
     const bool own = t < 3 * v.RG && i < 3LL * v.NS;
     if (own) bv = v.b[i];
     const RestrictLoads pl = restrict_load(v, g);
+    restrict_ready(pl);
     if (own) {
         v.r[i] = bv;
         v.x[i] = 0.0;
     }
     if (t < 3 * v.RG) rs[t] = bv;
-    const GroupUnits gu = restrict_stage(v, g, pl, sm + 3 * v.RG);
-    const double bb = block_sum(bv * bv, scratch);  // its barriers also publish rs and the plan
+    const double bb = block_sum(bv * bv, scratch);  // its barriers also publish rs
     if (t == 0) {
         v.P_rr[g] = bb;
         v.P_bb[g] = bb;
     }
-    restrict_group(v, gu, rs, sm + 3 * v.RG);
+    restrict_group_any(v, g, pl, rs, sm + 3 * v.RG, v.r1, v.cpart);
 }
 
 // Iteration k: alpha = rho_{k-1} / sigma_k (sigma summed here from the group
@@ -139,6 +139,7 @@ __global__ void k_update(SolverView v, int k) {
         return;
     }
     const double alpha = rho / sigma;
+    restrict_ready(pl);
     double rv = 0.0;
     if (own) {
         v.x[i] = xv + alpha * pv;
@@ -146,11 +147,10 @@ __global__ void k_update(SolverView v, int k) {
         v.r[i] = rv;
     }
     if (t < 3 * v.RG) rs[t] = rv;
-    const GroupUnits gu = restrict_stage(v, g, pl, sm + 3 * v.RG);
-    // its barriers also publish rs and the plan; scratch is not used again
+    // its barriers also publish rs; scratch is not used again
     const double rr = block_sum<false>(rv * rv, scratch);
     if (t == 0) v.P_rr[g] = rr;
-    restrict_group(v, gu, rs, sm + 3 * v.RG);
+    restrict_group_any(v, g, pl, rs, sm + 3 * v.RG, v.r1, v.cpart);
 }
 
 // Restriction of the current r only (preconditioner apply outside PCG).
@@ -162,9 +162,8 @@ __global__ void k_restrict(SolverView v) {
     const double rv = (t < 3 * v.RG && i < 3LL * v.NS) ? v.r[i] : 0.0;
     const RestrictLoads pl = restrict_load(v, g);
     if (t < 3 * v.RG) rs[t] = rv;
-    const GroupUnits gu = restrict_stage(v, g, pl, sm + 3 * v.RG);
     __syncthreads();
-    restrict_group(v, gu, rs, sm + 3 * v.RG);
+    restrict_group_any(v, g, pl, rs, sm + 3 * v.RG, v.r1, v.cpart);
 }
 
 // dL/dH_ij = -lambda_i x_j^T on every stored block, caller order and layout.

@@ -293,7 +293,8 @@ class MasPcg:
         check("mas_get_timings", self._L.mas_get_timings(self._h, out))
         return list(out)
 
-    KERNEL_SLOTS = ("spmv", "update", "apply_coarse", "apply_level0", "update_p", "residual", "permute_H", "restrict")
+    KERNEL_SLOTS = ("spmv", "update", "apply_coarse", "apply_level0", "level0_update", "residual", "permute_H",
+                    "restrict")
 
     def set_kernel_timing(self, enable=True):
         check("mas_set_kernel_timing", self._L.mas_set_kernel_timing(self._h, int(bool(enable))))

@@ -7,6 +7,9 @@ fixing a variant; this one is used for the synthetic systems only).  Each
 12x12 element Hessian is projected to PSD by clamping eigenvalues at zero.
 """
 
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 
 
@@ -66,12 +69,13 @@ def deformation_gradient(x, tets, D):
     return np.einsum("nai,naj->nij", x[tets], D)
 
 
-def snh_element_hessians(rest, x, tets, E, nu, chunk=65536):
+def snh_element_hessians(rest, x, tets, E, nu, chunk=16384):
     """PSD-projected 12x12 SNH Hessians (rest-volume weighted), per tet."""
     mu, lam = lame(E, nu)
     D, vol = shape_gradients(rest, tets)
     out = np.empty((tets.shape[0], 12, 12))
-    for s in range(0, tets.shape[0], chunk):
+
+    def one(s):  # chunks are independent: the result does not depend on the thread count
         e = slice(s, min(s + chunk, tets.shape[0]))
         F = deformation_gradient(x, tets[e], D[e])
         H9, _, _ = snh_dPsi_dF2(F, mu, lam)
@@ -84,6 +88,10 @@ def snh_element_hessians(rest, x, tets, E, nu, chunk=65536):
         w, V = np.linalg.eigh(K)
         w = np.maximum(w, 0.0) * vol[e][:, None]
         out[e] = np.einsum("nij,nj,nkj->nik", V, w, V)
+
+    starts = range(0, tets.shape[0], chunk)
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        list(ex.map(one, starts))
     return out, vol
 
 

@@ -169,16 +169,19 @@ def test_mas_apply_dense_operator_tiny(dev):
 # ------------------------------------------------------------------- PCG ---
 
 
+# every: period of the iterations that restrict r_k directly (50: all ten by
+# the coarse recurrence, 1: none, 3: the two kinds interleaved)
+@pytest.mark.parametrize("every", [50, 3, 1])
 @pytest.mark.parametrize("name,N", [("cube2", 4), ("cube3_stiff", 4), ("cube8", 16), ("rand300", 8), ("contact6", 16)])
-def test_pcg_fixed_iterations(dev, name, N):
-    _say("pcg fixed 10", name, N)
+def test_pcg_fixed_iterations(dev, name, N, every):
+    _say("pcg fixed 10", name, N, every)
     s = SYSTEMS[name]()
     P = _oracle(s, N)
     xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
     S = _solver(s, N)
     H = _H(s, dev)
     S.build(H)
-    x, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10)
+    x, res = S.solve(H, _t(s.b, dev), tol=0.0, max_iter=10, replace_every=every)
     assert res["iterations"] == it == 10 and res["status"] == 1
     x = x.cpu().numpy()
     assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
@@ -276,6 +279,33 @@ def test_pcg_edge_cases(dev):
     with pytest.raises(MasError) as e:
         S.build(Hb)
     assert e.value.code == -2
+
+
+def test_pcg_breakdown_on_indefinite_coupling(dev):
+    """p^T H p <= 0 inside PCG (every domain matrix SPD): the solve stops
+    with NOT_SPD after 0 iterations and x untouched, as the oracle does; the
+    eigenvector right-hand side converges in one iteration to b / 3."""
+    from paper_2411_06224_amd import BlockMatrix, MasError, MasPcg
+
+    _say("pcg breakdown on indefinite coupling")
+    I3 = np.eye(3)
+    row_ptr = np.array([0, 2, 4], dtype=np.int32)
+    col_idx = np.array([0, 1, 0, 1], dtype=np.int32)
+    val = np.stack([I3, 2 * I3, 2 * I3, I3])
+    H = BlockMatrix.from_numpy(row_ptr, col_idx, val, device=dev)
+    for every in (50, 1):  # the recurrence iteration and the direct one
+        S = MasPcg(row_ptr, col_idx, domain_size=1, poison=True)
+        S.build(H)
+        b = np.array([1.0, 0, 0, -1.0, 0, 0])
+        xr, st, it, *_ = oracle.MAS(row_ptr, col_idx, val, N=1).pcg(b, tol=1e-10)
+        assert st == oracle.NOT_SPD and it == 0
+        with pytest.raises(MasError) as e:
+            S.solve(H, _t(b, dev), tol=1e-10, replace_every=every, allow_not_converged=False)
+        assert e.value.code == -2
+        x, res = S.solve(H, _t(np.array([1.0, 0, 0, 1.0, 0, 0]), dev), tol=1e-10, replace_every=every)
+        assert res["status"] == 0 and res["iterations"] == 1
+        assert np.allclose(x.cpu().numpy(), np.array([1.0, 0, 0, 1.0, 0, 0]) / 3.0, rtol=0, atol=1e-15)
+        S.close()
 
 
 def test_pcg_single_domain_one_iteration(dev):

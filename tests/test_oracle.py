@@ -388,6 +388,28 @@ def test_pcg_edge_cases():
     assert Pb.status == oracle.NOT_SPD
 
 
+def test_pcg_breakdown_on_indefinite_coupling():
+    """sigma = p^T H p <= 0 stops PCG with NOT_SPD (O9) while every domain
+    matrix is SPD: two nodes, H = [[I, 2I], [2I, I]] (eigenvalues 3 and -1),
+    domains of one node (3x3 block Jacobi, M^-1 = I).  With b = (e1, -e1):
+    z = p = b and H p = (-e1, e1), so p^T H p = -2 at the first iteration;
+    with b = (e1, e1) the first direction is an eigenvector of eigenvalue 3
+    and the solve ends in one iteration with x = b / 3."""
+    I3 = np.eye(3)
+    row_ptr = np.array([0, 2, 4], dtype=np.int32)
+    col_idx = np.array([0, 1, 0, 1], dtype=np.int32)
+    val = np.stack([I3, 2 * I3, 2 * I3, I3])
+    P = oracle.MAS(row_ptr, col_idx, val, N=1)
+    assert P.status == oracle.OK
+    b = np.array([1.0, 0, 0, -1.0, 0, 0])
+    x, st, it, *_ = P.pcg(b, tol=1e-10)
+    assert st == oracle.NOT_SPD and it == 0 and not x.any()
+    b = np.array([1.0, 0, 0, 1.0, 0, 0])
+    x, st, it, *_ = P.pcg(b, tol=1e-10)
+    assert st == oracle.OK and it == 1
+    assert np.allclose(x, b / 3.0, rtol=0, atol=1e-15)
+
+
 # -------------------------------------------------------- adjoint (O11) ---
 
 
