@@ -31,6 +31,7 @@ COPY_BYTES = 256 << 20  # calibration copy: bytes read (and written) per copy
 KERNEL_SOURCES = {
     "spmv": ["spmv.hip", "common.hpp", "launch.hpp", "restrict.hpp"],
     "apply_level0": ["mas.hip", "common.hpp", "launch.hpp"],
+    "level0_update": ["mas.hip", "common.hpp", "launch.hpp"],
 }
 
 

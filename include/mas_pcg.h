@@ -67,6 +67,10 @@ enum {
 };
 
 #define MAS_MAX_LEVELS 16
+/* The batched inversion keeps a domain's 3N x 3N FP64 matrix, padded to
+ * 16 x 16 tiles, in one workgroup's LDS (160 KB per CU): 3N <= 128, so
+ * N <= 42; 40 is the largest size the tests cover.  The paper's N = 16
+ * (Sec. 4.2) is the default; 64 would need a 192 x 192 matrix (288 KB). */
 #define MAS_MAX_DOMAIN_SIZE 40
 
 /* A 3x3-block CSR matrix in device memory (layout above). */
