@@ -664,10 +664,36 @@ def run_configs(args, s1, H1, b1, dev, x_oracle):
     bm = torch.as_tensor(sm.b, device=dev)
     mean, med, res, _ = gpu_solves(mp, sm, Hm, bm, 1e-4, steps)
     e = gpu_entry(mean, med, res)
+    e["levels"] = mp.MasPcg(sm.row_ptr, sm.col_idx, graph=(sm.gptr, sm.gadj), domain_size=16).info()["levels"]
     xo = with_oracle(e, sm, 1e-4)
     cfg["membrane512_bodies2000_f64_tol1e-4"] = e
     f64_ms = mean
     log("membrane f64:", json.dumps(e))
+    # ordering ablation on this system (Sec. 4.1): level-0 domains of 16
+    # consecutive nodes in Morton order against the connectivity-aware
+    # partition; the bodies' couplings reach sheet nodes anywhere on the sheet
+    t0 = time.perf_counter()
+    part = mp.morton_partition(sm.meta["positions"], 16, device=dev)
+    t_part = time.perf_counter() - t0
+    sv = mp.MasPcg(sm.row_ptr, sm.col_idx, domain_size=16, partition=part)
+    xm_ = torch.empty_like(bm)
+    for _ in range(2):
+        sv.build(Hm)
+        sv.solve(Hm, bm, tol=1e-4, out=xm_)
+    ms_m = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        sv.build(Hm)
+        _, mres = sv.solve(Hm, bm, tol=1e-4, out=xm_)
+        ms_m.append(1e3 * (time.perf_counter() - t0))
+    cfg["membrane512_bodies2000_ordering_ablation"] = {
+        "connectivity": {"iterations": e["iterations"], "ms": e["ms"], "levels": e["levels"]},
+        "morton": {"iterations": mres["iterations"], "ms": round(float(np.mean(ms_m)), 4),
+                   "true_rel_residual": mres["true_rel_residual"], "levels": sv.info()["levels"],
+                   "partition_ms": round(1e3 * t_part, 2)},
+    }
+    sv.close()
+    log("membrane ordering ablation:", json.dumps(cfg["membrane512_bodies2000_ordering_ablation"]))
     mean, med, res, xm = gpu_solves(mp, sm, Hm, bm, 1e-4, steps, precision="mixed")
     e = gpu_entry(mean, med, res)
     e["rel_err_vs_f64_oracle"] = rel(xm.cpu().numpy(), xo)

@@ -157,6 +157,26 @@ int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_
 int mas_analyze_partition(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr,
                           const int32_t* col_idx, const int32_t* part, int32_t n_parts);
 
+/* Device bytes of the scratch mas_morton_partition needs for n_rows nodes. */
+size_t mas_morton_workspace_size(int32_t n_rows);
+
+/* Level-0 domains of domain_size consecutive nodes in Morton (Z-order) of
+ * the node positions: the domain ordering of the earlier MAS preconditioner
+ * that the connectivity-aware partition replaces (Sec. 4.1), for
+ * mas_analyze_partition.  Each coordinate is scaled to 21 bits over the
+ * bounding box, ((x - lo) / extent) * (2^21 - 1) rounded down (extent at
+ * least the smallest positive double), and the bits are interleaved x, y, z
+ * (x most significant) into a 63-bit code; nodes are ordered by code, equal
+ * codes by node id, and the k-th node goes to domain k / domain_size.
+ *   positions: device, 3*n_rows doubles (node-major).
+ *   part: device, n_rows int32 (output).
+ *   workspace: device scratch of ws_bytes >= mas_morton_workspace_size,
+ *              256-byte aligned.
+ * Asynchronous.  Errors: MAS_INVALID_ARG, MAS_WORKSPACE_TOO_SMALL,
+ * MAS_HIP_ERROR. */
+int mas_morton_partition(int32_t n_rows, const double* positions, int32_t domain_size, int32_t* part,
+                         void* workspace, size_t ws_bytes, void* stream);
+
 /* Device bytes the handle needs (valid after mas_analyze; 0 before). */
 size_t mas_workspace_size(const mas_handle* h);
 

@@ -9,7 +9,7 @@ fails loudly if the library has not been built.
 from ._lib import LibraryMissing, MasError, load
 from .solver import BlockMatrix, MasPcg, bcsr_assemble, bcsr_assemble_noalloc, bcsr_spmv
 from .autograd import MasPcgSolve, mas_pcg_solve
-from .ordering import morton_codes, morton_partition
+from .ordering import morton_partition
 
 __all__ = [
     "BlockMatrix",
@@ -19,7 +19,6 @@ __all__ = [
     "bcsr_assemble_noalloc",
     "MasPcgSolve",
     "mas_pcg_solve",
-    "morton_codes",
     "morton_partition",
     "LibraryMissing",
     "MasError",

@@ -28,6 +28,8 @@ SYMBOLS = (
     "mas_destroy",
     "mas_analyze",
     "mas_analyze_partition",
+    "mas_morton_workspace_size",
+    "mas_morton_partition",
     "mas_workspace_size",
     "mas_build",
     "mas_apply",
@@ -133,6 +135,10 @@ def load():
     L.mas_analyze.restype = ctypes.c_int
     L.mas_analyze_partition.argtypes = [vp, i32, i32, vp, vp, vp, i32]
     L.mas_analyze_partition.restype = ctypes.c_int
+    L.mas_morton_workspace_size.argtypes = [i32]
+    L.mas_morton_workspace_size.restype = sz
+    L.mas_morton_partition.argtypes = [i32, vp, i32, vp, vp, sz, vp]
+    L.mas_morton_partition.restype = ctypes.c_int
     L.mas_workspace_size.argtypes = [vp]
     L.mas_workspace_size.restype = sz
     L.mas_build.argtypes = [vp, P(MasBcsr), vp, sz, vp]

@@ -12,6 +12,7 @@
 
 #include "../../include/mas_pcg.h"
 #include "launch.hpp"
+#include "morton.hpp"
 #include "planner.hpp"
 #include "restrict.hpp"
 
@@ -807,6 +808,24 @@ int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
     if (ws_bytes < bcsr_assemble_workspace_size(n_rows, n_in)) return MAS_WORKSPACE_TOO_SMALL;
     return assemble_impl(n_rows, n_in, rows, cols, blocks, row_ptr, col_idx, val, capacity, nnzb,
                          static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+}
+
+size_t mas_morton_workspace_size(int32_t n_rows) {
+    if (n_rows < 1) return 0;
+    size_t total = 0;
+    morton_layout(nullptr, n_rows, &total);
+    return total;
+}
+
+int mas_morton_partition(int32_t n_rows, const double* positions, int32_t domain_size, int32_t* part,
+                         void* workspace, size_t ws_bytes, void* stream) {
+    if (n_rows < 1 || domain_size < 1 || !positions || !part || !workspace) return MAS_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < mas_morton_workspace_size(n_rows)) return MAS_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const MortonLayout L = morton_layout(static_cast<char*>(workspace), n_rows, nullptr);
+    HIP_TRY(launch_morton_partition(L, n_rows, domain_size, positions, part, s));
+    return MAS_OK;
 }
 
 int bcsr_assemble_noalloc(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols,

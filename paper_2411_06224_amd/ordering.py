@@ -1,37 +1,35 @@
-"""Alternative level-0 domain orderings for ``MasPcg(partition=...)``."""
+"""Level-0 domain orderings for ``MasPcg(partition=...)`` computed by the
+library (argument marshalling only)."""
+
+import ctypes
 
 import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_ALIGN = 256
 
 
-def _spread3(v):
-    """Spreads the low 21 bits of v so that bit i lands on bit 3 i."""
-    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
-    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
-    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
-    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
-    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
-    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
-    return v
-
-
-def morton_codes(positions):
-    """63-bit Morton (Z-order) codes of 3-D points: each coordinate scaled to
-    21 bits over the bounding box, bits interleaved x, y, z."""
-    p = np.asarray(positions, dtype=np.float64).reshape(-1, 3)
-    lo = p.min(axis=0)
-    ext = np.maximum(p.max(axis=0) - lo, np.finfo(np.float64).tiny)
-    q = np.floor((p - lo) / ext * ((1 << 21) - 1)).astype(np.int64)
-    q = np.clip(q, 0, (1 << 21) - 1)
-    return (_spread3(q[:, 0]) << np.uint64(2)) | (_spread3(q[:, 1]) << np.uint64(1)) | _spread3(q[:, 2])
-
-
-def morton_partition(positions, domain_size=16):
+def morton_partition(positions, domain_size=16, device=None):
     """Level-0 domains of ``domain_size`` consecutive nodes in Morton order of
     their positions (ties by node id): the domain ordering of the earlier MAS
-    preconditioner that the connectivity-aware partition replaces (Sec. 4.1).
-    Returns part[V] for ``MasPcg(partition=...)`` / mas_analyze_partition."""
-    codes = morton_codes(positions)
-    order = np.lexsort((np.arange(codes.size), codes))
-    part = np.empty(codes.size, dtype=np.int32)
-    part[order] = np.arange(codes.size) // domain_size
-    return part
+    preconditioner that the connectivity-aware partition replaces (Sec. 4.1),
+    computed on the device by mas_morton_partition.  ``positions``: [V, 3]
+    array or tensor.  Returns part[V] (numpy int32) for
+    ``MasPcg(partition=...)``."""
+    L = _lib.load()
+    if device is None:
+        device = positions.device if isinstance(positions, torch.Tensor) and positions.is_cuda else torch.device("cuda")
+    pos = torch.as_tensor(positions, dtype=torch.float64, device=device).reshape(-1, 3).contiguous()
+    n = pos.shape[0]
+    need = int(L.mas_morton_workspace_size(n))
+    ws = torch.empty(need + _ALIGN, dtype=torch.uint8, device=device)
+    wsp = (ws.data_ptr() + _ALIGN - 1) // _ALIGN * _ALIGN
+    part = torch.empty(n, dtype=torch.int32, device=device)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    rc = L.mas_morton_partition(n, ctypes.c_void_p(pos.data_ptr()), int(domain_size), ctypes.c_void_p(part.data_ptr()),
+                                ctypes.c_void_p(wsp), need, stream)
+    check("mas_morton_partition", rc)
+    return part.cpu().numpy().astype(np.int32)

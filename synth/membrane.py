@@ -236,6 +236,17 @@ def membrane_system(
         parts_c.append(ent[:, eb].ravel())
         parts_b.append(C[:, ea, eb].reshape(-1, 3, 3))
         meta["attach"] = attach
+    # positions (for the Morton ordering only): sheet nodes on the z = 0
+    # plane; a body's four block rows at the centroid of the sheet nodes it
+    # couples to, one body side above the sheet
+    pos = np.zeros((V, 3))
+    pos[:Vs, :2] = X[:, :2]
+    if n_bodies:
+        cen = X[attach][:, :, :2].mean(axis=1)
+        for p4 in range(4):
+            pos[base + p4, :2] = cen
+            pos[base + p4, 2] = body_side
+    meta["positions"] = pos
 
     all_r, all_c, all_b = np.concatenate(parts_r), np.concatenate(parts_c), np.concatenate(parts_b)
     del parts_r, parts_c, parts_b

@@ -92,6 +92,35 @@ def test_hierarchy_device_given_partition(dev):
     _check(S, P, dev)
 
 
+def test_morton_partition_matches_reference(dev):
+    """The device Morton partition (mas_morton_partition) against the numpy
+    definition in tests/morton_reference.py, bit for bit: lattice and noisy
+    cube positions, random points, a flat set (zero extent in z), duplicate
+    positions (ties broken by node id), one node, and domain sizes that do
+    not divide the node count."""
+    from paper_2411_06224_amd import morton_partition
+    from morton_reference import morton_partition as reference
+
+    _say("morton partition")
+    rng = np.random.default_rng(17)
+    flat = rng.uniform(-1.0, 1.0, (997, 3))
+    flat[:, 2] = 0.25
+    dup = np.repeat(rng.uniform(0.0, 1.0, (50, 3)), 7, axis=0)[rng.permutation(350)]
+    cases = [
+        (small_cube().meta["positions"], 16),
+        (large_cube().meta["positions"], 16),
+        (rng.uniform(-3.0, 7.0, (10007, 3)), 16),
+        (flat, 7),
+        (dup, 5),
+        (np.array([[0.5, -1.0, 2.0]]), 16),
+        (rng.standard_normal((4099, 3)) * 1e-9, 40),
+    ]
+    for pos, N in cases:
+        got = morton_partition(pos, N, device=dev)
+        ref = reference(pos, N)
+        assert got.dtype == np.int32 and np.array_equal(got, ref), (len(pos), N)
+
+
 def test_hierarchy_device_repeated_calls(dev):
     """The scratch is reused: a second call (and one after a solver build on
     another workspace) gives the same hierarchy."""

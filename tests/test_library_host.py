@@ -153,7 +153,7 @@ def _morton_bruteforce(q):
 
 
 def test_morton_codes_match_bitwise_interleave():
-    from paper_2411_06224_amd import morton_codes
+    from morton_reference import morton_codes
 
     rng = np.random.default_rng(3)
     pts = rng.uniform(-2.0, 5.0, size=(200, 3))
@@ -173,7 +173,7 @@ def test_given_partition_bit_exact_with_oracle():
     """Morton-ordered level-0 domains (the earlier MAS ordering, Sec. 4.1)
     through mas_analyze_partition: slots, supernodes and levels as the oracle
     builds them from the same partition."""
-    from paper_2411_06224_amd import morton_partition
+    from morton_reference import morton_partition
 
     for s, N in ((small_cube(), 16), (cube(6, E=1e6, nu=0.49, seed=21, n_contacts=60), 16), (small_cube(), 4)):
         part = morton_partition(s.meta["positions"], N)
