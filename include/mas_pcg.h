@@ -157,6 +157,44 @@ int mas_analyze(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_
 int mas_analyze_partition(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr,
                           const int32_t* col_idx, const int32_t* part, int32_t n_parts);
 
+/* Device bytes of the scratch abd_contact_blocks needs. */
+size_t abd_contact_workspace_size(int32_t n_nodes, int64_t m);
+
+/* Contact Hessian blocks on affine bodies mapped to the system's DOF blocks
+ * with the two-level reduction of Sec. 6.1 ("Two-Level Reduction for ABD
+ * Hessian Assembly"; sub-block decomposition of Sec. 6.2).  A contact node
+ * i either belongs to an affine body (node_is_body[i] != 0), whose 12 DOFs
+ * [t, a1, a2, a3] are the four block rows node_row[i] .. node_row[i] + 3 and
+ * which moves the node as x = t + A xbar_i (xbar_i = node_xbar[3i..3i+2],
+ * the rest position in the body frame), or is a node of the deformable mesh
+ * with block row node_row[i].  Block C_k couples nodes r[k] (rows) and c[k]
+ * (columns) and contributes J_r^T C_k J_c with J = [I | xbar1 I | xbar2 I |
+ * xbar3 I] for a body node and J = I for a mesh node, i.e. the 3x3
+ * sub-blocks (a, b) = (w_a(r) w_b(c)) C_k with w = (1, xbar1, xbar2, xbar3):
+ * 16 for a body-body pair, 4 for body-mesh or mesh-body, 1 for mesh-mesh.
+ *   levels = 2: the blocks of equal node pair (r, c) are first summed in
+ *     list order, and each distinct pair is mapped once; levels = 1: every
+ *     listed block is mapped (single-level).
+ * Output: the sub-block list (rows, cols, row-major 3x3 blocks), pairs in
+ * (r, c) order (levels = 2) or list order (levels = 1), sub-blocks (a, b)
+ * row-major within a pair; *n_out receives their number (also when it
+ * exceeds capacity).  The second level -- equal DOF blocks summed, e.g. all
+ * node pairs of one body pair -- is bcsr_assemble of this list together with
+ * the system's other blocks.
+ *   node_row, node_is_body: device int32[n_nodes]; node_xbar: device
+ *   double[3 n_nodes]; r, c: device int32[m], 0 <= index < n_nodes;
+ *   C: device double[9 m]; out_rows, out_cols: device int32[capacity];
+ *   out_blocks: device double[9 capacity].
+ *   workspace: device scratch of ws_bytes >= abd_contact_workspace_size,
+ *              256-byte aligned.
+ * Limits: n_nodes + 1 <= 2^20, 16 m < 2^31.  Synchronises the stream.
+ * Errors: MAS_INVALID_ARG (an index out of range, n_out > capacity: then
+ * nothing is written), MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
+int abd_contact_blocks(int32_t n_nodes, const int32_t* node_row, const int32_t* node_is_body,
+                       const double* node_xbar, int64_t m, const int32_t* r, const int32_t* c, const double* C,
+                       int32_t levels, int32_t* out_rows, int32_t* out_cols, double* out_blocks, int64_t capacity,
+                       int64_t* n_out, void* workspace, size_t ws_bytes, void* stream);
+
 /* Device bytes of the scratch mas_morton_partition needs for n_rows nodes. */
 size_t mas_morton_workspace_size(int32_t n_rows);
 
@@ -238,7 +276,8 @@ size_t bcsr_assemble_workspace_size(int32_t n_rows, int64_t n_in);
 /* Assembles a list of 3x3 blocks into 3x3-block CSR on the device: the
  * operation the hash-based parallel reduction of Sec. 6.2 performs (blocks
  * with the same (row, col) summed; rows ascending, columns ascending within
- * a row), here deterministic: equal blocks are summed in list order, so the
+ * a row), here deterministic: a stable radix sort of (row, col) keys keeps
+ * equal blocks in list order and each is summed in that order, so the
  * result is that of a sequential pass over the list.
  *   rows, cols: device int32[n_in], 0 <= index < n_rows.
  *   blocks: device double[9 n_in], row-major 3x3 blocks.
@@ -248,10 +287,10 @@ size_t bcsr_assemble_workspace_size(int32_t n_rows, int64_t n_in);
  *         exceeds capacity, so the caller can size the outputs).
  *   workspace: device scratch of ws_bytes >= bcsr_assemble_workspace_size,
  *              256-byte aligned.
- * Limits: n_in < 2^31, n_rows + 1 <= 2^20, at most 4096 listed blocks per
- * row.  Synchronises the stream.  Errors: MAS_INVALID_ARG (an index out of
- * range, a limit exceeded, nnzb > capacity: then col_idx and val are not
- * written), MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
+ * Limits: n_in < 2^31, n_rows + 1 <= 2^20.  Synchronises the stream.
+ * Errors: MAS_INVALID_ARG (an index out of range, a limit exceeded,
+ * nnzb > capacity: then col_idx and val are not written),
+ * MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
 int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
                   int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb,
                   void* workspace, size_t ws_bytes, void* stream);

@@ -84,6 +84,8 @@ def lib():
         L.orc_adjoint_scatter.argtypes = [_i, _pi, _pi, _pd, _pd, _pd]
         L.orc_assemble.argtypes = [_i, ctypes.c_long, _pi, _pi, _pd, _pi, _pi, _pd]
         L.orc_assemble.restype = ctypes.c_long
+        L.orc_abd_expand.argtypes = [_i, _pi, _pi, _pd, ctypes.c_long, _pi, _pi, _pd, _pi, _pi, _pd]
+        L.orc_abd_expand.restype = ctypes.c_long
         _lib = L
     return _lib
 
@@ -168,6 +170,26 @@ def assemble(n, rows, cols, blocks):
     if nb < 0:
         raise ValueError("block index out of range")
     return row_ptr, col_idx[:nb], val[:nb]
+
+
+def abd_expand(node_row, node_is_body, node_xbar, rows, cols, blocks):
+    """Contact blocks on affine bodies as DOF-block sub-blocks (J_r^T C J_c of
+    every listed block, list order, Sec. 6.1): (rows, cols, blocks[n, 3, 3])."""
+    nr, nrp = _ci(node_row)
+    nb_, nbp = _ci(node_is_body)
+    xb, xbp = _cd(np.asarray(node_xbar, dtype=np.float64).reshape(-1))
+    r, rp = _ci(rows)
+    c, cp = _ci(cols)
+    b, bp = _cd(np.asarray(blocks, dtype=np.float64).reshape(-1))
+    m = r.size
+    out_r = np.zeros(16 * max(m, 1), dtype=np.int32)
+    out_c = np.zeros(16 * max(m, 1), dtype=np.int32)
+    out_b = np.zeros((16 * max(m, 1), 3, 3))
+    k = lib().orc_abd_expand(int(nr.size), nrp, nbp, xbp, m, rp, cp, bp, out_r.ctypes.data_as(_pi),
+                             out_c.ctypes.data_as(_pi), out_b.ctypes.data_as(_pd))
+    if k < 0:
+        raise ValueError("node index out of range")
+    return out_r[:k], out_c[:k], out_b[:k]
 
 
 class MAS:

@@ -713,3 +713,32 @@ long orc_assemble(int n, long n_in, const int* rows, const int* cols, const doub
     free(e);
     return nb;
 }
+
+/* Contact Hessian blocks on affine bodies in DOF-block coordinates, the plain
+ * definition behind the two-level reduction of Sec. 6.1: listed block C_k
+ * between contact nodes r_k and c_k contributes J_r^T C_k J_c, where a node
+ * of an affine body (is_body) has J = [I | xbar1 I | xbar2 I | xbar3 I]
+ * (x = t + A xbar; its body's 12 DOFs are block rows row .. row + 3) and a
+ * mesh node has J = I (block row row).  Sub-block (a, b) of the product is
+ * (w_a(r) w_b(c)) C_k with w = (1, xbar1, xbar2, xbar3).  Writes the
+ * sub-blocks of every listed block in list order, (a, b) row-major, and
+ * returns their number, or -1 for a node index out of range. */
+long orc_abd_expand(int n_nodes, const int* node_row, const int* is_body, const double* xbar, long m, const int* r,
+                    const int* c, const double* C, int* out_rows, int* out_cols, double* out_blocks) {
+    long o = 0;
+    for (long k = 0; k < m; ++k) {
+        if (r[k] < 0 || r[k] >= n_nodes || c[k] < 0 || c[k] >= n_nodes) return -1;
+        const int nr = is_body[r[k]] ? 4 : 1, nc = is_body[c[k]] ? 4 : 1;
+        for (int a = 0; a < nr; ++a)
+            for (int b = 0; b < nc; ++b) {
+                const double wa = a == 0 ? 1.0 : xbar[3L * r[k] + a - 1];
+                const double wb = b == 0 ? 1.0 : xbar[3L * c[k] + b - 1];
+                const double w = wa * wb;
+                out_rows[o] = node_row[r[k]] + a;
+                out_cols[o] = node_row[c[k]] + b;
+                for (int e = 0; e < 9; ++e) out_blocks[9 * o + e] = w * C[9 * k + e];
+                ++o;
+            }
+    }
+    return o;
+}

@@ -104,6 +104,11 @@ void orc_adjoint_scatter(int n, const int* rp, const int* ci, const double* lamb
 long orc_assemble(int n, long n_in, const int* rows, const int* cols, const double* blocks, int* row_ptr,
                   int* col_idx, double* val);
 
+/* Contact blocks on affine bodies in DOF-block coordinates (Sec. 6.1):
+ * every listed block's J_r^T C J_c sub-blocks, in list order. */
+long orc_abd_expand(int n_nodes, const int* node_row, const int* is_body, const double* xbar, long m, const int* r,
+                    const int* c, const double* C, int* out_rows, int* out_cols, double* out_blocks);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,7 +7,7 @@ fails loudly if the library has not been built.
 """
 
 from ._lib import LibraryMissing, MasError, load
-from .solver import BlockMatrix, MasPcg, bcsr_assemble, bcsr_assemble_noalloc, bcsr_spmv
+from .solver import BlockMatrix, MasPcg, abd_contact_blocks, bcsr_assemble, bcsr_assemble_noalloc, bcsr_spmv
 from .autograd import MasPcgSolve, mas_pcg_solve
 from .ordering import morton_partition
 
@@ -17,6 +17,7 @@ __all__ = [
     "bcsr_spmv",
     "bcsr_assemble",
     "bcsr_assemble_noalloc",
+    "abd_contact_blocks",
     "MasPcgSolve",
     "mas_pcg_solve",
     "morton_partition",

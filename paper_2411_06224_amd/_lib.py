@@ -37,6 +37,8 @@ SYMBOLS = (
     "bcsr_assemble_workspace_size",
     "bcsr_assemble",
     "bcsr_assemble_noalloc",
+    "abd_contact_workspace_size",
+    "abd_contact_blocks",
     "pcg_solve",
     "pcg_adjoint",
     "mas_hierarchy_workspace_size",
@@ -155,6 +157,11 @@ def load():
     L.bcsr_assemble_noalloc.argtypes = [i32, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_int64,
                                         P(ctypes.c_int64), vp]
     L.bcsr_assemble_noalloc.restype = ctypes.c_int
+    L.abd_contact_workspace_size.argtypes = [i32, ctypes.c_int64]
+    L.abd_contact_workspace_size.restype = ctypes.c_size_t
+    L.abd_contact_blocks.argtypes = [i32, vp, vp, vp, ctypes.c_int64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_int64,
+                                     P(ctypes.c_int64), vp, ctypes.c_size_t, vp]
+    L.abd_contact_blocks.restype = ctypes.c_int
     L.mas_hierarchy_workspace_size.argtypes = [vp]
     L.mas_hierarchy_workspace_size.restype = ctypes.c_size_t
     L.mas_hierarchy_device.argtypes = [vp, vp, vp, vp, vp, ctypes.c_size_t, vp]

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/mas_pcg.h"
+#include "abd.hpp"
 #include "launch.hpp"
 #include "morton.hpp"
 #include "planner.hpp"
@@ -746,16 +747,14 @@ int assemble_impl(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
                   int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity, int64_t* nnzb, char* ws,
                   hipStream_t s) {
     const AsmLayout L = assemble_layout(ws, n_rows, n_in, nullptr);
-    HIP_TRY(launch_assemble_count(L, n_rows, n_in, rows, cols, s));
-    HIP_TRY(launch_scan(L.ucnt, n_rows, row_ptr, L.totals, s));
-    int host[3] = {0, 0, 0};
+    HIP_TRY(launch_assemble_sort(L, n_rows, n_in, rows, cols, row_ptr, s));
+    int host[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(host, L.flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(host + 2, row_ptr + n_rows, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (host[0]) return MAS_INVALID_ARG;  // index out of range / row over the limit
-    *nnzb = host[2];
-    if (host[2] > capacity || (host[2] > 0 && (!col_idx || !val))) return MAS_INVALID_ARG;
-    HIP_TRY(launch_assemble_reduce(L, n_rows, blocks, row_ptr, col_idx, val, s));
+    if (host[0]) return MAS_INVALID_ARG;  // an index out of range
+    *nnzb = host[1];
+    if (host[1] > capacity || (host[1] > 0 && (!col_idx || !val))) return MAS_INVALID_ARG;
+    HIP_TRY(launch_assemble_reduce(L, n_in, blocks, col_idx, val, host[1], s));
     HIP_TRY(hipStreamSynchronize(s));
     return MAS_OK;
 }
@@ -808,6 +807,59 @@ int bcsr_assemble(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
     if (ws_bytes < bcsr_assemble_workspace_size(n_rows, n_in)) return MAS_WORKSPACE_TOO_SMALL;
     return assemble_impl(n_rows, n_in, rows, cols, blocks, row_ptr, col_idx, val, capacity, nnzb,
                          static_cast<char*>(workspace), static_cast<hipStream_t>(stream));
+}
+
+size_t abd_contact_workspace_size(int32_t n_nodes, int64_t m) {
+    if (n_nodes < 1 || m < 0) return 0;
+    size_t total = 0;
+    abd_layout(nullptr, n_nodes, m, &total);
+    return total;
+}
+
+int abd_contact_blocks(int32_t n_nodes, const int32_t* node_row, const int32_t* node_is_body,
+                       const double* node_xbar, int64_t m, const int32_t* r, const int32_t* c, const double* C,
+                       int32_t levels, int32_t* out_rows, int32_t* out_cols, double* out_blocks, int64_t capacity,
+                       int64_t* n_out, void* workspace, size_t ws_bytes, void* stream) {
+    if (n_nodes < 1 || n_nodes + 1 > (1 << 20) || m < 0 || m > 0x7fffffffLL / 16 || capacity < 0 || !n_out ||
+        !node_row || !node_is_body || !node_xbar || !workspace || (levels != 1 && levels != 2))
+        return MAS_INVALID_ARG;
+    if (m > 0 && (!r || !c || !C)) return MAS_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < abd_contact_workspace_size(n_nodes, m)) return MAS_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const AbdLayout L = abd_layout(static_cast<char*>(workspace), n_nodes, m, nullptr);
+    const int *pr = r, *pc = c;
+    const double* pv = C;
+    long long np = m;
+    if (levels == 2) {
+        // first level: equal node pairs summed in list order (block-list
+        // assembly over the contact nodes)
+        int64_t pairs = 0;
+        const int rc = assemble_impl(n_nodes, m, r, c, C, L.row_ptr, L.pair_col, L.pair_val, m, &pairs,
+                                     static_cast<char*>(L.asm_ws), s);
+        if (rc != MAS_OK) return rc;
+        HIP_TRY(launch_abd_pair_rows(L, n_nodes, s));
+        pr = L.pair_row;
+        pc = L.pair_col;
+        pv = L.pair_val;
+        np = pairs;
+    } else {
+        HIP_TRY(launch_abd_check(L, m, n_nodes, r, c, s));
+        int bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, L.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return MAS_INVALID_ARG;
+    }
+    HIP_TRY(launch_abd_count(L, np, pr, pc, node_is_body, s));
+    int total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, L.off + np, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_out = total;
+    if (total > capacity || (total > 0 && (!out_rows || !out_cols || !out_blocks))) return MAS_INVALID_ARG;
+    HIP_TRY(launch_abd_expand(L, np, pr, pc, pv, node_row, node_is_body, node_xbar, out_rows, out_cols, out_blocks,
+                              s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MAS_OK;
 }
 
 size_t mas_morton_workspace_size(int32_t n_rows) {

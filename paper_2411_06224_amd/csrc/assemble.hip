@@ -2,11 +2,17 @@
 // reduction of Sec. 6.2 computes: the blocks of equal (row, col) key meet
 // contiguously after sorting by key and are reduced segment by segment).
 //
-// Deterministic, without sorting keys globally: the blocks are counted and
-// scattered per row (atomic slots, any order), each row's entries are then
-// sorted in LDS by (column, position in the list), and every (row, col)
-// segment is summed in list order by one thread.  The sums are therefore
-// those of a sequential pass over the list.
+// Each listed block gets the key (row << 20) | col; a stable radix sort of
+// (key, list position) pairs (rocPRIM) places equal keys together in list
+// order; segment heads and their exclusive scan number the distinct blocks;
+// each distinct block is summed over its segment in list order, nine
+// threads per block.  The sums are those of a sequential pass over the
+// list, and no row length is limited.
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
+
 #include "launch.hpp"
 
 namespace maspcg {
@@ -14,23 +20,11 @@ namespace {
 
 constexpr int kAsmThreads = 256;
 constexpr int kScanItems = 1024;  // elements per block of the scan
+constexpr int kKeyBits = 40;      // row and column below 2^20 each
 
 __global__ void k_fill_int(int* __restrict__ p, long long n, int value) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = value;
-}
-
-// cnt[row]++ for every listed block; an index out of range raises flag bit 0.
-__global__ void k_asm_count(long long n_in, int n_rows, const int* __restrict__ rows, const int* __restrict__ cols,
-                            int* __restrict__ cnt, int* __restrict__ flag) {
-    const long long k = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= n_in) return;
-    const int r = rows[k], c = cols[k];
-    if (r < 0 || r >= n_rows || c < 0 || c >= n_rows) {
-        atomicOr(flag, 1);
-        return;
-    }
-    atomicAdd(cnt + r, 1);
 }
 
 // Exclusive scan of n ints: per-block scans with block totals (pass 1), a
@@ -97,137 +91,111 @@ __global__ void k_scan_add(int* __restrict__ out, int n, const int* __restrict__
     for (int j = i; j < min(n, static_cast<int>(blockIdx.x + 1) * kScanItems); j += blockDim.x) out[j] += add;
 }
 
-// Every listed block into a slot of its row (order within the row arbitrary);
-// blocks with an index out of range were not counted and are skipped.
-__global__ void k_asm_scatter(long long n_in, int n_rows, const int* __restrict__ rows, const int* __restrict__ cols,
-                              const int* __restrict__ start, int* __restrict__ fill, int* __restrict__ perm) {
-    const long long k = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+// Key and list position of every listed block; an index out of range
+// raises flag bit 0 (its key sorts last and is never reduced).
+__global__ void __launch_bounds__(kAsmThreads) k_asm_keys(long long n_in, int n_rows, const int* __restrict__ rows,
+                                                          const int* __restrict__ cols, uint64_t* __restrict__ key,
+                                                          int* __restrict__ pos, int* __restrict__ flag) {
+    const long long k = static_cast<long long>(blockIdx.x) * kAsmThreads + threadIdx.x;
     if (k >= n_in) return;
     const int r = rows[k], c = cols[k];
-    if (r < 0 || r >= n_rows || c < 0 || c >= n_rows) return;
-    perm[start[r] + atomicAdd(fill + r, 1)] = static_cast<int>(k);
+    const bool bad = r < 0 || r >= n_rows || c < 0 || c >= n_rows;
+    if (bad) atomicOr(flag, 1);
+    key[k] = bad ? (1ull << kKeyBits) - 1 : (static_cast<uint64_t>(r) << 20) | static_cast<uint64_t>(c);
+    pos[k] = static_cast<int>(k);
 }
 
-constexpr int kMaxRowEntries = 4096;  // listed blocks per row sorted in LDS
+__global__ void __launch_bounds__(kAsmThreads) k_asm_heads(long long n_in, const uint64_t* __restrict__ key,
+                                                           int* __restrict__ head) {
+    const long long k = static_cast<long long>(blockIdx.x) * kAsmThreads + threadIdx.x;
+    if (k < n_in) head[k] = (k == 0 || key[k] != key[k - 1]) ? 1 : 0;
+}
 
-// One workgroup per row: bitonic sort of the row's entries by (column,
-// position in the list) in LDS; sorted positions back to perm, sorted
-// columns to scol, the number of distinct columns to ucnt[row].  A row with
-// more than kMaxRowEntries entries raises flag bit 1.
-__global__ void __launch_bounds__(kAsmThreads) k_asm_sort(int n_rows, const int* __restrict__ cols,
-                                                          const int* __restrict__ start, int* __restrict__ perm,
-                                                          int* __restrict__ scol, int* __restrict__ ucnt,
+// Segment starts, row pointers and the number of distinct blocks.  Row r
+// begins at the segment of its first sorted entry; rows without blocks take
+// the next row's start (every row_ptr entry has one writer).
+__global__ void __launch_bounds__(kAsmThreads) k_asm_rows(long long n_in, int n_rows, const uint64_t* __restrict__ key,
+                                                          const int* __restrict__ head, const int* __restrict__ seg,
+                                                          int* __restrict__ seg_start, int* __restrict__ row_ptr,
                                                           int* __restrict__ flag) {
-    __shared__ unsigned long long key[kMaxRowEntries];
-    __shared__ int heads[kAsmThreads];
-    const int row = blockIdx.x, t = threadIdx.x;
-    const int s0 = start[row], m = start[row + 1] - s0;
-    if (m > kMaxRowEntries) {
-        if (t == 0) {
-            atomicOr(flag, 2);
-            ucnt[row] = 0;
-        }
+    const long long k = static_cast<long long>(blockIdx.x) * kAsmThreads + threadIdx.x;
+    if (n_in == 0) {
+        for (long long r = k; r <= n_rows; r += static_cast<long long>(gridDim.x) * kAsmThreads) row_ptr[r] = 0;
+        if (k == 0) flag[1] = 0;
         return;
     }
-    int n = 1;
-    while (n < m) n <<= 1;
-    for (int i = t; i < n; i += kAsmThreads) {
-        unsigned long long kv = ~0ull;
-        if (i < m) {
-            const int p = perm[s0 + i];
-            kv = (static_cast<unsigned long long>(static_cast<unsigned int>(cols[p])) << 32) | static_cast<unsigned int>(p);
-        }
-        key[i] = kv;
+    if (k >= n_in) return;
+    const uint64_t kk = key[k];
+    const bool valid = kk < (1ull << kKeyBits) - 1;
+    const int r = static_cast<int>(kk >> 20);
+    if (head[k] && valid) {
+        seg_start[seg[k]] = static_cast<int>(k);
+        const int pr = k == 0 ? -1 : static_cast<int>(key[k - 1] >> 20);
+        for (int rr = pr + 1; rr <= r; ++rr) row_ptr[rr] = seg[k];
     }
-    __syncthreads();
-    for (int k = 2; k <= n; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < n; i += kAsmThreads) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long a = key[i], b = key[ixj];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        key[i] = b;
-                        key[ixj] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    // the last valid entry closes the remaining rows and counts the blocks
+    const bool last = valid && (k + 1 == n_in || key[k + 1] >= (1ull << kKeyBits) - 1);
+    if (last) {
+        const int total = seg[k] + head[k];
+        for (int rr = r + 1; rr <= n_rows; ++rr) row_ptr[rr] = total;
+        seg_start[total] = static_cast<int>(k + 1);
+        flag[1] = total;
     }
-    int h = 0;
-    for (int i = t; i < m; i += kAsmThreads) {
-        const unsigned long long kv = key[i];
-        perm[s0 + i] = static_cast<int>(kv & 0xffffffffu);
-        scol[s0 + i] = static_cast<int>(kv >> 32);
-        h += (i == 0 || (key[i - 1] >> 32) != (kv >> 32)) ? 1 : 0;
-    }
-    heads[t] = h;
-    __syncthreads();
-    if (t == 0) {
-        int s = 0;
-        for (int q = 0; q < kAsmThreads; ++q) s += heads[q];
-        ucnt[row] = s;
+    if (k == 0 && !valid) {  // every index out of range: nothing to assemble
+        for (int rr = 0; rr <= n_rows; ++rr) row_ptr[rr] = 0;
+        flag[1] = 0;
     }
 }
 
-// One workgroup per row: thread t owns the sorted entries [t c, (t+1) c) of
-// the row (c = ceil(m / threads)); every segment head it owns sums its
-// segment in order and writes block row_ptr[row] + rank.
-__global__ void __launch_bounds__(kAsmThreads) k_asm_reduce(int n_rows, const int* __restrict__ start,
-                                                            const int* __restrict__ perm, const int* __restrict__ scol,
+// Distinct block b = t / 9, entry t % 9: the sum over its segment in list
+// order (nine consecutive threads read one listed block).
+__global__ void __launch_bounds__(kAsmThreads) k_asm_reduce(int nnzb, const uint64_t* __restrict__ key,
+                                                            const int* __restrict__ pos,
+                                                            const int* __restrict__ seg_start,
                                                             const double* __restrict__ blocks,
-                                                            const int* __restrict__ row_ptr, int* __restrict__ col_idx,
-                                                            double* __restrict__ val) {
-    __shared__ int sh[kAsmThreads];
-    const int row = blockIdx.x, t = threadIdx.x;
-    const int s0 = start[row], m = start[row + 1] - s0;
-    if (m == 0 || m > kMaxRowEntries) return;
-    const int per = (m + kAsmThreads - 1) / kAsmThreads;
-    const int e0 = min(m, t * per), e1 = min(m, e0 + per);
-    int h = 0;
-    for (int e = e0; e < e1; ++e) h += (e == 0 || scol[s0 + e - 1] != scol[s0 + e]) ? 1 : 0;
-    int total;
-    int rank = block_exclusive_scan(h, sh, total);
-    const long long out0 = row_ptr[row];
-    for (int e = e0; e < e1; ++e) {
-        const int c = scol[s0 + e];
-        if (e != 0 && scol[s0 + e - 1] == c) continue;
-        double acc[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-        for (int f = e; f < m && scol[s0 + f] == c; ++f) {
-            const double* b = blocks + 9LL * perm[s0 + f];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) acc[q] += b[q];
-        }
-        const long long o = out0 + rank;
-        col_idx[o] = c;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) val[9 * o + q] = acc[q];
-        ++rank;
-    }
+                                                            int* __restrict__ col_idx, double* __restrict__ val) {
+    const long long t = static_cast<long long>(blockIdx.x) * kAsmThreads + threadIdx.x;
+    if (t >= 9LL * nnzb) return;
+    const int b = static_cast<int>(t / 9), c = static_cast<int>(t - 9LL * b);
+    const int e0 = seg_start[b], e1 = seg_start[b + 1];
+    double acc = 0.0;
+    for (int e = e0; e < e1; ++e) acc += blocks[9LL * pos[e] + c];
+    val[9LL * b + c] = acc;
+    if (c == 0) col_idx[b] = static_cast<int>(key[e0] & 0xFFFFFull);
+}
+
+size_t tmp_bytes(long long n_in) {
+    const int n = static_cast<int>(std::max<long long>(n_in, 1));
+    size_t sb = 0, cb = 0;
+    rocprim::radix_sort_pairs(nullptr, sb, static_cast<uint64_t*>(nullptr), static_cast<uint64_t*>(nullptr),
+                              static_cast<int*>(nullptr), static_cast<int*>(nullptr), n, 0, kKeyBits);
+    rocprim::exclusive_scan(nullptr, cb, static_cast<int*>(nullptr), static_cast<int*>(nullptr), 0, n,
+                            rocprim::plus<int>());
+    return std::max(sb, cb);
 }
 
 }  // namespace
 
 AsmLayout assemble_layout(char* ws, int n_rows, long long n_in, size_t* total) {
+    (void)n_rows;
     size_t off = 0;
-    auto take = [&](size_t count) {
-        int* p = reinterpret_cast<int*>(ws ? ws + off : nullptr);
-        off += (sizeof(int) * count + 255) / 256 * 256;
+    auto take = [&](size_t bytes) {
+        char* p = ws ? ws + off : nullptr;
+        off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
         return p;
     };
-    const size_t rows1 = static_cast<size_t>(n_rows) + 1, m = n_in > 0 ? static_cast<size_t>(n_in) : 1;
-    AsmLayout L;
-    L.cnt = take(rows1);
-    L.start = take(rows1);
-    L.ucnt = take(rows1);
-    L.perm = take(m);
-    L.scol = take(m);
-    L.totals = take((rows1 + kScanItems - 1) / kScanItems + 1);
-    L.flag = take(2);
+    const size_t m = n_in > 0 ? static_cast<size_t>(n_in) : 1;
+    AsmLayout L{};
+    L.key = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * m));
+    L.key_sorted = reinterpret_cast<uint64_t*>(take(sizeof(uint64_t) * m));
+    L.pos = reinterpret_cast<int*>(take(sizeof(int) * m));
+    L.pos_sorted = reinterpret_cast<int*>(take(sizeof(int) * m));
+    L.head = reinterpret_cast<int*>(take(sizeof(int) * m));
+    L.seg = reinterpret_cast<int*>(take(sizeof(int) * m));
+    L.seg_start = reinterpret_cast<int*>(take(sizeof(int) * (m + 1)));
+    L.flag = reinterpret_cast<int*>(take(sizeof(int) * 2));
+    L.tmp_bytes = tmp_bytes(n_in);
+    L.tmp = take(L.tmp_bytes);
     if (total) *total = off;
     return L;
 }
@@ -241,32 +209,43 @@ hipError_t launch_scan(const int* in, int n, int* out, int* totals, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_assemble_count(const AsmLayout& L, int n_rows, long long n_in, const int* rows, const int* cols,
-                                 hipStream_t s) {
-    const int fb = ceil_div(n_rows + 1, kAsmThreads);
-    launch_kernel(k_fill_int, dim3(fb), dim3(kAsmThreads), 0, s, L.cnt, static_cast<long long>(n_rows + 1), 0);
-    launch_kernel(k_fill_int, dim3(1), dim3(kAsmThreads), 0, s, L.flag, 2LL, 0);
-    if (n_in > 0)
-        launch_kernel(k_asm_count, dim3(ceil_div(n_in, kAsmThreads)), dim3(kAsmThreads), 0, s, n_in, n_rows, rows, cols,
-                      L.cnt, L.flag);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // start = exclusive scan of the counts; cnt is then reused as the fill counters
-    if ((e = launch_scan(L.cnt, n_rows, L.start, L.totals, s)) != hipSuccess) return e;
-    launch_kernel(k_fill_int, dim3(fb), dim3(kAsmThreads), 0, s, L.cnt, static_cast<long long>(n_rows + 1), 0);
-    if (n_in > 0)
-        launch_kernel(k_asm_scatter, dim3(ceil_div(n_in, kAsmThreads)), dim3(kAsmThreads), 0, s, n_in, n_rows, rows,
-                      cols, static_cast<const int*>(L.start), L.cnt, L.perm);
-    launch_kernel(k_asm_sort, dim3(n_rows), dim3(kAsmThreads), 0, s, n_rows, cols, static_cast<const int*>(L.start),
-                  L.perm, L.scol, L.ucnt, L.flag);
+hipError_t launch_assemble_sort(const AsmLayout& L, int n_rows, long long n_in, const int* rows, const int* cols,
+                                int* row_ptr, hipStream_t s) {
+    launch_kernel(k_fill_int, dim3(1), dim3(64), 0, s, L.flag, 2LL, 0);
+    hipError_t e;
+    if (n_in > 0) {
+        const int g = ceil_div(n_in, kAsmThreads);
+        launch_kernel(k_asm_keys, dim3(g), dim3(kAsmThreads), 0, s, n_in, n_rows, rows, cols, L.key, L.pos, L.flag);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        size_t bytes = L.tmp_bytes;
+        if ((e = rocprim::radix_sort_pairs(L.tmp, bytes, L.key, L.key_sorted, L.pos, L.pos_sorted,
+                                           static_cast<int>(n_in), 0, kKeyBits, s)) != hipSuccess)
+            return e;
+        launch_kernel(k_asm_heads, dim3(g), dim3(kAsmThreads), 0, s, n_in, static_cast<const uint64_t*>(L.key_sorted),
+                      L.head);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        bytes = L.tmp_bytes;
+        if ((e = rocprim::exclusive_scan(L.tmp, bytes, L.head, L.seg, 0, static_cast<int>(n_in),
+                                         rocprim::plus<int>(), s)) != hipSuccess)
+            return e;
+        launch_kernel(k_asm_rows, dim3(g), dim3(kAsmThreads), 0, s, n_in, n_rows,
+                      static_cast<const uint64_t*>(L.key_sorted), static_cast<const int*>(L.head),
+                      static_cast<const int*>(L.seg), L.seg_start, row_ptr, L.flag);
+    } else {
+        launch_kernel(k_asm_rows, dim3(ceil_div(n_rows + 1, kAsmThreads)), dim3(kAsmThreads), 0, s, 0LL, n_rows,
+                      static_cast<const uint64_t*>(L.key_sorted), static_cast<const int*>(L.head),
+                      static_cast<const int*>(L.seg), L.seg_start, row_ptr, L.flag);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_assemble_reduce(const AsmLayout& L, int n_rows, const double* blocks, int* row_ptr, int* col_idx,
-                                  double* val, hipStream_t s) {
-    launch_kernel(k_asm_reduce, dim3(n_rows), dim3(kAsmThreads), 0, s, n_rows, static_cast<const int*>(L.start),
-                  static_cast<const int*>(L.perm), static_cast<const int*>(L.scol), blocks,
-                  static_cast<const int*>(row_ptr), col_idx, val);
+hipError_t launch_assemble_reduce(const AsmLayout& L, long long n_in, const double* blocks, int* col_idx, double* val,
+                                  int nnzb, hipStream_t s) {
+    (void)n_in;
+    if (nnzb <= 0) return hipSuccess;
+    launch_kernel(k_asm_reduce, dim3(ceil_div(9LL * nnzb, kAsmThreads)), dim3(kAsmThreads), 0, s, nnzb,
+                  static_cast<const uint64_t*>(L.key_sorted), static_cast<const int*>(L.pos_sorted),
+                  static_cast<const int*>(L.seg_start), blocks, col_idx, val);
     return hipGetLastError();
 }
 

@@ -187,20 +187,27 @@ hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, h
 
 // assemble.hip: block-list assembly (scratch in the caller's workspace).
 struct AsmLayout {
-    int *cnt, *start, *ucnt, *perm, *scol, *totals, *flag;
+    uint64_t *key, *key_sorted;  // (row << 20) | col per listed block
+    int *pos, *pos_sorted;       // list position of each listed block
+    int *head, *seg;             // segment heads of the sorted list and their exclusive scan
+    int *seg_start;              // first sorted entry of each distinct (row, col)
+    int* flag;                   // [0]: bit 0 index out of range; [1]: distinct blocks
+    void* tmp;                   // radix sort / scan scratch of tmp_bytes
+    size_t tmp_bytes;
 };
 // Layout of the assembly scratch from ws (ws = nullptr: sizes only; *total
 // receives the bytes needed).
 AsmLayout assemble_layout(char* ws, int n_rows, long long n_in, size_t* total);
 // Exclusive scan of n ints into out[0..n] (out[n] = total); n + 1 <= 2^20.
 hipError_t launch_scan(const int* in, int n, int* out, int* totals, hipStream_t s);
-// Counts, scatters and sorts the listed blocks per row; flag bit 0: index
-// out of range, bit 1: a row with more than 4096 listed blocks.
-hipError_t launch_assemble_count(const AsmLayout& L, int n_rows, long long n_in, const int* rows, const int* cols,
-                                 hipStream_t s);
-// Sums every (row, col) segment in list order into row_ptr / col_idx / val.
-hipError_t launch_assemble_reduce(const AsmLayout& L, int n_rows, const double* blocks, int* row_ptr, int* col_idx,
-                                  double* val, hipStream_t s);
+// Keys, stable sort by (row, col) and segment heads of the listed blocks;
+// row_ptr of the result; flag[0] bit 0: index out of range, flag[1]: the
+// number of distinct blocks.
+hipError_t launch_assemble_sort(const AsmLayout& L, int n_rows, long long n_in, const int* rows, const int* cols,
+                                int* row_ptr, hipStream_t s);
+// Sums every (row, col) segment in list order into col_idx / val.
+hipError_t launch_assemble_reduce(const AsmLayout& L, long long n_in, const double* blocks, int* col_idx, double* val,
+                                  int nnzb, hipStream_t s);
 
 // hierarchy.hip: supernode hierarchy on the device.
 struct HierLayout {

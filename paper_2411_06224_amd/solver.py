@@ -150,6 +150,36 @@ def bcsr_assemble_noalloc(n_rows, rows, cols, blocks, row_ptr, col_idx, val):
     return int(nb.value)
 
 
+def abd_contact_blocks(n_nodes, node_row, node_is_body, node_xbar, rows, cols, blocks, levels=2):
+    """Contact blocks on affine bodies mapped to DOF blocks (two-level
+    reduction, Sec. 6.1): returns (rows, cols, blocks[n, 3, 3]) on the
+    device, ready for bcsr_assemble with the system's other blocks.
+    node_row / node_is_body: int32 [n_nodes]; node_xbar: float64
+    [n_nodes, 3]; rows / cols: int32 [m] node indices; blocks: float64
+    [m, 3, 3]; levels: 2 (pairs reduced first) or 1 (every block mapped)."""
+    for t, name, dt in ((node_row, "node_row", torch.int32), (node_is_body, "node_is_body", torch.int32),
+                        (node_xbar, "node_xbar", torch.float64), (rows, "rows", torch.int32),
+                        (cols, "cols", torch.int32), (blocks, "blocks", torch.float64)):
+        _need_cuda(t, name, dt)
+    m = rows.numel()
+    L = _lib.load()
+    dev = rows.device
+    need = int(L.abd_contact_workspace_size(int(n_nodes), m))
+    ws = torch.empty(need + _ALIGN, dtype=torch.uint8, device=dev)
+    wsp = (ws.data_ptr() + _ALIGN - 1) // _ALIGN * _ALIGN
+    cap = 16 * max(m, 1)
+    out_r = torch.empty(cap, dtype=torch.int32, device=dev)
+    out_c = torch.empty(cap, dtype=torch.int32, device=dev)
+    out_b = torch.empty((cap, 3, 3), dtype=torch.float64, device=dev)
+    n = ctypes.c_int64(0)
+    rc = L.abd_contact_blocks(int(n_nodes), _ptr(node_row), _ptr(node_is_body), _ptr(node_xbar), m, _ptr(rows),
+                              _ptr(cols), _ptr(blocks), int(levels), _ptr(out_r), _ptr(out_c), _ptr(out_b), cap,
+                              ctypes.byref(n), ctypes.c_void_p(wsp), need, _stream())
+    check("abd_contact_blocks", rc)
+    k = n.value
+    return out_r[:k], out_c[:k], out_b[:k]
+
+
 class MasPcg:
     """MAS-preconditioned PCG for one sparsity pattern.
 

@@ -76,10 +76,14 @@ def test_assemble_list_order_and_edges(dev):
     cols = np.arange(40) // 10
     blocks = np.random.default_rng(3).standard_normal((40, 3, 3))
     _same(_gpu(10, rows, cols, blocks, dev, capacity=3), oracle.assemble(10, rows, cols, blocks))
-    # a row with more listed blocks than the per-row sort holds
-    many = 5000
-    with pytest.raises(MasError):
-        _gpu(4, np.zeros(many), np.arange(many) % 4, np.ones((many, 3, 3)), dev)
+    # one long row (no per-row limit): 20,000 listed blocks over four columns
+    many = 20000
+    rows, cols = np.zeros(many, dtype=np.int64), np.arange(many) % 4
+    blocks = np.random.default_rng(5).standard_normal((many, 3, 3))
+    _same(_gpu(4, rows, cols, blocks, dev), oracle.assemble(4, rows, cols, blocks))
+    # rows before, between and after the listed ones stay empty
+    _same(_gpu(9, [7, 2, 7], [3, 8, 3], np.stack([one, 2 * one, 3 * one]), dev),
+          oracle.assemble(9, [7, 2, 7], [3, 8, 3], np.stack([one, 2 * one, 3 * one])))
 
 
 def test_assemble_cube_blocks(dev):
