@@ -317,7 +317,8 @@ int bcsr_assemble_noalloc(int32_t n_rows, int64_t n_in, const int32_t* rows, con
                           const double* blocks, int32_t* row_ptr, int32_t* col_idx, double* val, int64_t capacity,
                           int64_t* nnzb, void* stream);
 
-/* Device bytes of scratch mas_hierarchy_device needs (after mas_analyze). */
+/* Device bytes of scratch mas_hierarchy_device and mas_hierarchy_rebuild
+ * need (after mas_analyze). */
 size_t mas_hierarchy_workspace_size(const mas_handle* h);
 
 /* The supernode hierarchy computed on the device (Supp. Alg. 2-5, with
@@ -338,6 +339,29 @@ size_t mas_hierarchy_workspace_size(const mas_handle* h);
  * MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
 int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t* sn, void* workspace,
                          size_t ws_bytes, void* stream);
+
+/* The supernode hierarchy of a new block pattern under the analysed level-0
+ * partition, built and left on the device: what Sec. 4.2 repeats every
+ * Newton iteration, when contacts change H's pattern while the partition
+ * computed at load stays (the construction of mas_hierarchy_device; every
+ * level is queued at once and a level state on the device ends the
+ * hierarchy, so nothing is read back to the host).
+ *   nnzb, row_ptr, col_idx: device, the new pattern in the caller's node
+ *       order (n_rows of the analysis; row_ptr[n_rows + 1], col_idx[nnzb]);
+ *       it is symmetrised (block (i, j) links both nodes), so one triangle
+ *       suffices; the diagonal is not needed.
+ *   out_units: device int32[MAS_MAX_LEVELS + 1]: [0] = the level count, or
+ *       -1 when a row range or a column index lies outside the pattern;
+ *       [1 + l] = units of level l (0 past the last level).
+ *   out_sn: device int32[MAS_MAX_LEVELS * n_rows]: unit of node i at level
+ *       l at [l * n_rows + i], -1 past the last level.
+ *   workspace: device scratch, ws_bytes >= mas_hierarchy_workspace_size,
+ *       256-byte aligned (not shared with a running call).
+ * The node -> slot map of the analysis is copied to the workspace from the
+ * handle on each call.  Does not synchronise the stream.  Errors:
+ * MAS_NOT_READY, MAS_INVALID_ARG, MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
+int mas_hierarchy_rebuild(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                          int32_t* out_units, int32_t* out_sn, void* workspace, size_t ws_bytes, void* stream);
 
 /* Host copy of the handle's static description (after mas_analyze). */
 int mas_get_info(const mas_handle* h, mas_info* out);

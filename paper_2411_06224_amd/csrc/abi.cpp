@@ -903,8 +903,37 @@ size_t mas_hierarchy_workspace_size(const mas_handle* h) {
     const Plan& P = h->plan;
     size_t t = 0;
     hierarchy_layout(nullptr, P.NS, kMaxLv, &t);
-    return t + round256(sizeof(int) * (P.NS + 1)) + round256(sizeof(int) * P.nnzb) + round256(sizeof(int) * P.NS);
+    return t + round256(sizeof(int) * (P.NS + 1)) + round256(sizeof(int) * P.nnzb) + round256(sizeof(int) * P.NS) +
+           round256(sizeof(int) * P.V);
 }
+
+namespace {
+
+struct HierWs {
+    HierLayout H;
+    int *rp, *ci, *remap, *map;
+};
+
+HierWs hier_ws(const Plan& P, char* ws) {
+    HierWs W;
+    size_t off = 0;
+    W.H = hierarchy_layout(ws, P.NS, kMaxLv, &off);
+    W.rp = reinterpret_cast<int*>(ws + off);
+    off += round256(sizeof(int) * (P.NS + 1));
+    W.ci = reinterpret_cast<int*>(ws + off);
+    off += round256(sizeof(int) * P.nnzb);
+    W.remap = reinterpret_cast<int*>(ws + off);
+    off += round256(sizeof(int) * P.NS);
+    W.map = reinterpret_cast<int*>(ws + off);
+    return W;
+}
+
+int hier_level_cap(const mas_handle* h) {
+    const int m = h->opts.max_levels;
+    return m > 0 ? std::min(m, kMaxLv) : kMaxLv;
+}
+
+}  // namespace
 
 int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t* sn, void* workspace,
                          size_t ws_bytes, void* stream) {
@@ -914,45 +943,46 @@ int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t
     if (ws_bytes < mas_hierarchy_workspace_size(h)) return MAS_WORKSPACE_TOO_SMALL;
     const Plan& P = h->plan;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    char* ws = static_cast<char*>(workspace);
-    size_t off = 0;
-    const HierLayout H = hierarchy_layout(ws, P.NS, kMaxLv, &off);
-    int* rp = reinterpret_cast<int*>(ws + off);
-    off += round256(sizeof(int) * (P.NS + 1));
-    int* ci = reinterpret_cast<int*>(ws + off);
-    off += round256(sizeof(int) * P.nnzb);
-    int* remap = reinterpret_cast<int*>(ws + off);
-    HIP_TRY(hipMemcpyAsync(rp, P.rp0.data(), sizeof(int) * (P.NS + 1), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(ci, P.ci0.data(), sizeof(int) * P.nnzb, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(remap, P.remap.data(), sizeof(int) * P.NS, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_hier_init(H, P.NS, remap, s));
-    std::vector<int> u(1, P.NS), nd(1, P.M);
-    int occupied = P.V;
-    const int max_levels = h->opts.max_levels;
-    for (int l = 0;; ++l) {
-        if (nd[l] == 1) break;
-        if (max_levels > 0 && l + 1 >= max_levels) break;
-        if (l + 1 >= kMaxLv) break;
-        HIP_TRY(launch_hier_level(H, l, P.NS, P.N, u[l], rp, ci, remap, s));
-        int S = 0;
-        HIP_TRY(hipMemcpyAsync(&S, H.off + nd[l], sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (S == occupied) break;  // nothing merged
-        u.push_back(S);
-        nd.push_back((S + P.N - 1) / P.N);
-        occupied = S;
-    }
-    const int L = static_cast<int>(u.size());
+    const HierWs W = hier_ws(P, static_cast<char*>(workspace));
+    HIP_TRY(hipMemcpyAsync(W.rp, P.rp0.data(), sizeof(int) * (P.NS + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.ci, P.ci0.data(), sizeof(int) * P.nnzb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.remap, P.remap.data(), sizeof(int) * P.NS, hipMemcpyHostToDevice, s));
+    const HierPattern pat{W.rp, W.ci, nullptr, P.nnzb};
+    HIP_TRY(launch_hierarchy(W.H, P.NS, P.V, P.N, hier_level_cap(h), W.remap, pat, s));
+    HierState st{};
+    HIP_TRY(hipMemcpyAsync(&st, W.H.st, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int L = st.levels;
     if (levels) *levels = L;
     if (units)
-        for (int l = 0; l < L; ++l) units[l] = u[l];
+        for (int l = 0; l < L; ++l) units[l] = st.units[l];
     if (sn) {
         std::vector<int> slot_sn(static_cast<size_t>(L) * P.NS);
-        HIP_TRY(hipMemcpyAsync(slot_sn.data(), H.sn, sizeof(int) * slot_sn.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(slot_sn.data(), W.H.sn, sizeof(int) * slot_sn.size(), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         for (int l = 0; l < L; ++l)
-            for (int i = 0; i < P.V; ++i) sn[static_cast<size_t>(l) * P.V + i] = slot_sn[static_cast<size_t>(l) * P.NS + P.map[i]];
+            for (int i = 0; i < P.V; ++i)
+                sn[static_cast<size_t>(l) * P.V + i] = slot_sn[static_cast<size_t>(l) * P.NS + P.map[i]];
     }
+    return MAS_OK;
+}
+
+int mas_hierarchy_rebuild(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
+                          int32_t* out_units, int32_t* out_sn, void* workspace, size_t ws_bytes, void* stream) {
+    if (!h) return MAS_INVALID_ARG;
+    if (!h->analyzed) return MAS_NOT_READY;
+    if (nnzb < 0 || nnzb > 0x7fffffffLL || !row_ptr || (nnzb > 0 && !col_idx) || !out_units || !out_sn)
+        return MAS_INVALID_ARG;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < mas_hierarchy_workspace_size(h)) return MAS_WORKSPACE_TOO_SMALL;
+    const Plan& P = h->plan;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const HierWs W = hier_ws(P, static_cast<char*>(workspace));
+    HIP_TRY(hipMemcpyAsync(W.remap, P.remap.data(), sizeof(int) * P.NS, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.map, P.map.data(), sizeof(int) * P.V, hipMemcpyHostToDevice, s));
+    const HierPattern pat{row_ptr, col_idx, W.map, nnzb};
+    HIP_TRY(launch_hierarchy(W.H, P.NS, P.V, P.N, hier_level_cap(h), W.remap, pat, s));
+    HIP_TRY(launch_hier_export(W.H, P.V, P.NS, W.map, out_units, out_sn, s));
     return MAS_OK;
 }
 

@@ -209,16 +209,37 @@ hipError_t launch_assemble_sort(const AsmLayout& L, int n_rows, long long n_in, 
 hipError_t launch_assemble_reduce(const AsmLayout& L, long long n_in, const double* blocks, int* col_idx, double* val,
                                   int nnzb, hipStream_t s);
 
-// hierarchy.hip: supernode hierarchy on the device.
+// hierarchy.hip: supernode hierarchy on the device, every level queued at
+// once; the level state on the device ends it (no host round trip).
+struct HierState {
+    int n_units;          // units of the current level
+    int occupied;         // occupied units of the current level
+    int levels;           // levels built so far
+    int done;             // 1: no further level
+    int bad;              // 1: the node-order pattern had an entry out of range
+    int units[kMaxLv];
+};
 struct HierLayout {
     unsigned long long* mask;
     int *sn, *rep, *up, *cnt, *off, *totals;
+    HierState* st;
+};
+// The pattern the hierarchy is built from: slot-ordered (map = null; rows
+// and columns are slots), or in the caller's node order with the node ->
+// slot map (nnzb blocks; checked against V).
+struct HierPattern {
+    const int *rp, *ci, *map;
+    long long nnzb;
 };
 HierLayout hierarchy_layout(char* ws, int NS, int L_max, size_t* total);
-hipError_t launch_hier_init(const HierLayout& H, int NS, const int* remap, hipStream_t s);
-// Level l -> l + 1 of the hierarchy: H.off[ceil(n_units / N)] receives the
-// number of next-level units, H.sn + (l + 1) NS the next unit of every slot.
-hipError_t launch_hier_level(const HierLayout& H, int l, int NS, int N, int n_units, const int* rp, const int* ci,
-                             const int* remap, hipStream_t s);
+// Levels 0 .. L_cap - 1 at most; H.sn + l NS receives the unit of every slot
+// at level l, H.st the level count and units.
+hipError_t launch_hierarchy(const HierLayout& H, int NS, int V, int N, int L_cap, const int* remap,
+                            const HierPattern& pat, hipStream_t s);
+// out_units[0] = levels (-1: invalid pattern), out_units[1 + l] = units of
+// level l (kMaxLv + 1 entries); out_sn[l V + i] = unit of node i at level l,
+// -1 past the last level (kMaxLv V entries).
+hipError_t launch_hier_export(const HierLayout& H, int V, int NS, const int* map, int* out_units, int* out_sn,
+                              hipStream_t s);
 
 }  // namespace maspcg

@@ -317,6 +317,34 @@ class MasPcg:
         L = levels.value
         return units[:L].copy(), sn[:L].copy()
 
+    def hierarchy_rebuild(self, row_ptr, col_idx):
+        """Supernode hierarchy of a new block pattern (device int32 row_ptr /
+        col_idx in node order, e.g. after contacts changed) under the analysed
+        partition, built on the device with no host round trip.
+
+        Returns device tensors ``(units[MAS_MAX_LEVELS + 1], sn[MAS_MAX_LEVELS,
+        V])``: ``units[0]`` is the level count (-1: an index outside the
+        pattern), ``units[1 + l]`` the units of level l; ``sn[l, i]`` the unit
+        of node i at level l (-1 past the last level).
+        """
+        _need_cuda(row_ptr, "row_ptr", torch.int32)
+        _need_cuda(col_idx, "col_idx", torch.int32)
+        if row_ptr.numel() != self.n_rows + 1:
+            raise ValueError("row_ptr must have n_rows + 1 entries")
+        dev = row_ptr.device
+        need = int(self._L.mas_hierarchy_workspace_size(self._h))
+        if need == 0:
+            raise MasError("mas_hierarchy_workspace_size", MAS_INVALID_ARG)
+        ws = torch.empty(need + _ALIGN, dtype=torch.uint8, device=dev)
+        base = (ws.data_ptr() + _ALIGN - 1) // _ALIGN * _ALIGN
+        units = torch.empty(_lib.MAS_MAX_LEVELS + 1, dtype=torch.int32, device=dev)
+        sn = torch.empty((_lib.MAS_MAX_LEVELS, self.n_rows), dtype=torch.int32, device=dev)
+        check("mas_hierarchy_rebuild",
+              self._L.mas_hierarchy_rebuild(self._h, col_idx.numel(), _ptr(row_ptr), _ptr(col_idx), _ptr(units),
+                                            _ptr(sn), ctypes.c_void_p(base), ctypes.c_size_t(need), _stream()))
+        self._hier_ws = ws  # kept until the next call: the queued kernels use it
+        return units, sn
+
     def timings(self):
         """Device ms of [coarse sums, inversion, H permute, PCG iterations] of the last calls."""
         out = (ctypes.c_double * 4)()

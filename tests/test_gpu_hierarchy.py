@@ -146,3 +146,137 @@ def test_hierarchy_device_large_cube(dev):
     S = MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16)
     units = _check(S, P, dev)
     print("units per level:", list(units))
+
+
+def _graph_pattern(s):
+    """Block pattern of the mesh graph alone (diagonal plus graph edges):
+    the pattern before any contact."""
+    n = s.n
+    rows = [np.arange(n)]
+    cols = [np.arange(n)]
+    deg = np.diff(s.gptr)
+    rows.append(np.repeat(np.arange(n), deg))
+    cols.append(s.gadj)
+    r = np.concatenate(rows).astype(np.int64)
+    c = np.concatenate(cols).astype(np.int64)
+    key = np.unique(r * n + c)
+    r, c = key // n, key % n
+    rp = np.zeros(n + 1, np.int32)
+    np.add.at(rp, r + 1, 1)
+    return np.cumsum(rp).astype(np.int32), c.astype(np.int32)
+
+
+def _upper(rp, ci):
+    n = rp.size - 1
+    r = np.repeat(np.arange(n), np.diff(rp))
+    keep = ci >= r
+    rp2 = np.zeros(n + 1, np.int32)
+    np.add.at(rp2, r[keep] + 1, 1)
+    return np.cumsum(rp2).astype(np.int32), ci[keep].astype(np.int32)
+
+
+def _check_rebuild(units_d, sn_d, P):
+    units = units_d.cpu().numpy()
+    sn = sn_d.cpu().numpy()
+    L = int(units[0])
+    assert L == P.levels
+    for l in range(L):
+        assert units[1 + l] == P.units(l), l
+        assert np.array_equal(sn[l], P.sn(l)), l
+    assert np.all(sn[L:] == -1) and np.all(units[1 + L:] == 0)
+
+
+def _add_pairs(rp, ci, n_pairs, seed):
+    """The pattern with n_pairs random node pairs added in both directions
+    (contacts appearing between Newton steps), and diagonally dominant
+    values on it (10 I on the diagonal, 0.01 I elsewhere: the hierarchy
+    depends on the pattern only)."""
+    n = rp.size - 1
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, n, n_pairs)
+    b = rng.integers(0, n, n_pairs)
+    r = np.concatenate([np.repeat(np.arange(n), np.diff(rp)), a, b]).astype(np.int64)
+    c = np.concatenate([ci, b, a]).astype(np.int64)
+    key = np.unique(r * n + c)
+    r, c = key // n, key % n
+    rp2 = np.zeros(n + 1, np.int32)
+    np.add.at(rp2, r + 1, 1)
+    val = np.where((r == c)[:, None, None], 10.0, 0.01) * np.eye(3)[None]
+    return np.cumsum(rp2).astype(np.int32), c.astype(np.int32), val
+
+
+REBUILD_CASES = {
+    "cube8_200": lambda: (small_cube(), 200),
+    "cube8_800": lambda: (small_cube(), 800),
+    "contact6_300": lambda: (cube(6, E=1e6, nu=0.49, seed=21, n_contacts=60), 300),
+    "local2000_500": lambda: (synth.random_spd_system(2000, 6000, seed=6, local=30), 500),
+}
+
+
+@pytest.mark.parametrize("name", list(REBUILD_CASES))
+@pytest.mark.parametrize("N", [16, 40])
+def test_hierarchy_rebuild_after_contact_change(dev, name, N):
+    """Analysed on the contact-free pattern; the hierarchy of the pattern
+    with new contacts, rebuilt on the device under the same partition,
+    equals the oracle's hierarchy of that pattern (whole or one triangle)."""
+    from paper_2411_06224_amd import MasPcg
+
+    _say("hierarchy rebuild", name, N)
+    s, n_pairs = REBUILD_CASES[name]()
+    rp1, ci1 = _graph_pattern(s)
+    rp2, ci2, val2 = _add_pairs(rp1, ci1, n_pairs, seed=N)
+    S = MasPcg(rp1, ci1, graph=(s.gptr, s.gadj), domain_size=N)
+    P = oracle.MAS(rp2, ci2, val2, N=N, gptr=s.gptr, gadj=s.gadj)
+    P1 = oracle.MAS(rp1, ci1, np.tile(np.eye(3), (ci1.size, 1, 1)) * 4.0, N=N, gptr=s.gptr, gadj=s.gadj)
+    if N == 16:  # there the new contacts change the hierarchy in every case
+        assert P.levels != P1.levels or any(not np.array_equal(P.sn(l), P1.sn(l)) for l in range(P.levels))
+    for rp, ci in ((rp2, ci2), _upper(rp2, ci2)):
+        units, sn = S.hierarchy_rebuild(torch.as_tensor(rp, device=dev), torch.as_tensor(ci, device=dev))
+        _check_rebuild(units, sn, P)
+    # the contact-free pattern gives the analysed hierarchy back
+    units, sn = S.hierarchy_rebuild(torch.as_tensor(rp1, device=dev), torch.as_tensor(ci1, device=dev))
+    _check_rebuild(units, sn, P1)
+    assert int(units[0]) == S.info()["levels"]
+
+
+@pytest.mark.parametrize("max_levels", [1, 2, 3])
+def test_hierarchy_rebuild_level_cap(dev, max_levels):
+    from paper_2411_06224_amd import MasPcg
+
+    _say("hierarchy rebuild cap", max_levels)
+    s, n_pairs = REBUILD_CASES["cube8_200"]()
+    rp1, ci1 = _graph_pattern(s)
+    rp2, ci2, val2 = _add_pairs(rp1, ci1, n_pairs, seed=3)
+    S = MasPcg(rp1, ci1, graph=(s.gptr, s.gadj), domain_size=16, max_levels=max_levels)
+    P = oracle.MAS(rp2, ci2, val2, N=16, max_levels=max_levels, gptr=s.gptr, gadj=s.gadj)
+    units, sn = S.hierarchy_rebuild(torch.as_tensor(rp2, device=dev), torch.as_tensor(ci2, device=dev))
+    _check_rebuild(units, sn, P)
+
+
+def test_hierarchy_rebuild_deep(dev):
+    """A pattern whose hierarchy reaches the level limit (16 levels)."""
+    from paper_2411_06224_amd import MasPcg
+
+    _say("hierarchy rebuild deep")
+    s = synth.random_spd_system(4000, 60000, seed=4)
+    S = MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16)
+    P = oracle.MAS(s.row_ptr, s.col_idx, s.val, N=16, gptr=s.gptr, gadj=s.gadj)
+    assert P.levels == 16
+    units, sn = S.hierarchy_rebuild(torch.as_tensor(s.row_ptr, device=dev), torch.as_tensor(s.col_idx, device=dev))
+    _check_rebuild(units, sn, P)
+
+
+def test_hierarchy_rebuild_rejects_out_of_range_columns(dev):
+    from paper_2411_06224_amd import MasPcg
+
+    _say("hierarchy rebuild bad pattern")
+    s = cube(6, E=1e6, nu=0.49, seed=21, n_contacts=60)
+    S = MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16)
+    ci = s.col_idx.copy()
+    ci[5] = s.n  # one column past the last node
+    units, _ = S.hierarchy_rebuild(torch.as_tensor(s.row_ptr, device=dev), torch.as_tensor(ci, device=dev))
+    assert int(units[0]) == -1
+    rp = s.row_ptr.copy()
+    rp[-1] = rp[-1] + 7  # row range past the column list
+    units, _ = S.hierarchy_rebuild(torch.as_tensor(rp, device=dev), torch.as_tensor(s.col_idx, device=dev))
+    assert int(units[0]) == -1
