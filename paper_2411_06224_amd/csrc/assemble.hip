@@ -19,6 +19,7 @@ namespace maspcg {
 namespace {
 
 constexpr int kAsmThreads = 256;
+constexpr int kAsmBatch = 4;  // listed blocks loaded together by the segment sums
 constexpr int kScanItems = 1024;  // elements per block of the scan
 constexpr int kKeyBits = 40;      // row and column below 2^20 each
 
@@ -148,7 +149,9 @@ __global__ void __launch_bounds__(kAsmThreads) k_asm_rows(long long n_in, int n_
 }
 
 // Distinct block b = t / 9, entry t % 9: the sum over its segment in list
-// order (nine consecutive threads read one listed block).
+// order (nine consecutive threads read one listed block).  The segment is
+// read kAsmBatch entries at a time: their positions, then their values, all
+// in flight together, then added in order.
 __global__ void __launch_bounds__(kAsmThreads) k_asm_reduce(int nnzb, const uint64_t* __restrict__ key,
                                                             const int* __restrict__ pos,
                                                             const int* __restrict__ seg_start,
@@ -159,7 +162,17 @@ __global__ void __launch_bounds__(kAsmThreads) k_asm_reduce(int nnzb, const uint
     const int b = static_cast<int>(t / 9), c = static_cast<int>(t - 9LL * b);
     const int e0 = seg_start[b], e1 = seg_start[b + 1];
     double acc = 0.0;
-    for (int e = e0; e < e1; ++e) acc += blocks[9LL * pos[e] + c];
+    for (int e = e0; e < e1; e += kAsmBatch) {
+        int p[kAsmBatch];
+#pragma unroll
+        for (int j = 0; j < kAsmBatch; ++j) p[j] = pos[min(e + j, e1 - 1)];
+        double x[kAsmBatch];
+#pragma unroll
+        for (int j = 0; j < kAsmBatch; ++j) x[j] = blocks[9LL * p[j] + c];
+#pragma unroll
+        for (int j = 0; j < kAsmBatch; ++j)
+            if (e + j < e1) acc += x[j];
+    }
     val[9LL * b + c] = acc;
     if (c == 0) col_idx[b] = static_cast<int>(key[e0] & 0xFFFFFull);
 }
