@@ -187,6 +187,8 @@ size_t abd_contact_workspace_size(int32_t n_nodes, int64_t m);
  *   out_blocks: device double[9 capacity].
  *   workspace: device scratch of ws_bytes >= abd_contact_workspace_size,
  *              256-byte aligned.
+ * node_row entries are not checked here (the DOF rows they produce are, by
+ * bcsr_assemble).
  * Limits: n_nodes + 1 <= 2^20, 16 m < 2^31.  Synchronises the stream.
  * Errors: MAS_INVALID_ARG (an index out of range, n_out > capacity: then
  * nothing is written), MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
@@ -357,8 +359,10 @@ int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t
  *       l at [l * n_rows + i], -1 past the last level.
  *   workspace: device scratch, ws_bytes >= mas_hierarchy_workspace_size,
  *       256-byte aligned (not shared with a running call).
- * The node -> slot map of the analysis is copied to the workspace from the
- * handle on each call.  Does not synchronise the stream.  Errors:
+ * The node -> slot map of the analysis is read from the solver's workspace
+ * once mas_build has placed the plans there (nothing is copied); before the
+ * first mas_build it is copied from the handle into this workspace on each
+ * call.  Does not synchronise the stream.  Errors:
  * MAS_NOT_READY, MAS_INVALID_ARG, MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
 int mas_hierarchy_rebuild(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
                           int32_t* out_units, int32_t* out_sn, void* workspace, size_t ws_bytes, void* stream);

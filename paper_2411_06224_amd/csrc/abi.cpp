@@ -978,11 +978,20 @@ int mas_hierarchy_rebuild(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, c
     const Plan& P = h->plan;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const HierWs W = hier_ws(P, static_cast<char*>(workspace));
-    HIP_TRY(hipMemcpyAsync(W.remap, P.remap.data(), sizeof(int) * P.NS, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(W.map, P.map.data(), sizeof(int) * P.V, hipMemcpyHostToDevice, s));
-    const HierPattern pat{row_ptr, col_idx, W.map, nnzb};
-    HIP_TRY(launch_hierarchy(W.H, P.NS, P.V, P.N, hier_level_cap(h), W.remap, pat, s));
-    HIP_TRY(launch_hier_export(W.H, P.V, P.NS, W.map, out_units, out_sn, s));
+    // the node -> slot map: from the solver's workspace once mas_build has
+    // placed the plans there, else copied from the handle
+    const int* remap = W.remap;
+    const int* map = W.map;
+    if (h->uploaded_to) {
+        remap = at<int>(h, h->lay.remap);
+        map = at<int>(h, h->lay.map);
+    } else {
+        HIP_TRY(hipMemcpyAsync(W.remap, P.remap.data(), sizeof(int) * P.NS, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(W.map, P.map.data(), sizeof(int) * P.V, hipMemcpyHostToDevice, s));
+    }
+    const HierPattern pat{row_ptr, col_idx, map, nnzb};
+    HIP_TRY(launch_hierarchy(W.H, P.NS, P.V, P.N, hier_level_cap(h), remap, pat, s));
+    HIP_TRY(launch_hier_export(W.H, P.V, P.NS, map, out_units, out_sn, s));
     return MAS_OK;
 }
 

@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
 
 // ------------------------------------------------------------------ apply
 constexpr int kFlagX0 = 1, kFlagMixed = 2, kFlagRrTrue = 4;
-constexpr int kRound = 4;  // coarse partials loaded per round by one lane
+constexpr int kRound = 8;  // coarse partials loaded per round by one lane
 
 // Workgroup 0 of the coarse launch takes the convergence decision of the
 // iteration: it sums the ||r||^2 partials (and ||b||^2 for the first
@@ -420,29 +420,27 @@ __global__ void __launch_bounds__(256) k_apply_coarse(SolverView v, DomTable tab
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         if (a < nu) {
             // the lane's partials m0 + sub, + 16, + 32, ... in this order;
-            // kRound are loaded per round so that their latencies overlap (a
-            // unit of the top levels has partials from about a hundred groups)
+            // kRound are loaded per round (at clamped indices, the ones past
+            // the range not added) so that their latencies overlap: a unit of
+            // the top levels has partials from about a hundred groups, which
+            // one round then covers
             const int m0 = cp[u0 + a], m1 = cp[u0 + a + 1];
-            int m = m0 + sub;
-            for (; m + 16 * (kRound - 1) < m1; m += 16 * kRound) {
+            for (int m = m0 + sub; m < m1; m += 16 * kRound) {
                 double a0[kRound], a1[kRound], a2[kRound];
 #pragma unroll
                 for (int j = 0; j < kRound; ++j) {
-                    a0[j] = part[3 * (m + 16 * j)];
-                    a1[j] = part[3 * (m + 16 * j) + 1];
-                    a2[j] = part[3 * (m + 16 * j) + 2];
+                    const int mj = min(m + 16 * j, m1 - 1);
+                    a0[j] = part[3 * mj];
+                    a1[j] = part[3 * mj + 1];
+                    a2[j] = part[3 * mj + 2];
                 }
 #pragma unroll
-                for (int j = 0; j < kRound; ++j) {
-                    s0 += a0[j];
-                    s1 += a1[j];
-                    s2 += a2[j];
-                }
-            }
-            for (; m < m1; m += 16) {
-                s0 += part[3 * m];
-                s1 += part[3 * m + 1];
-                s2 += part[3 * m + 2];
+                for (int j = 0; j < kRound; ++j)
+                    if (m + 16 * j < m1) {
+                        s0 += a0[j];
+                        s1 += a1[j];
+                        s2 += a2[j];
+                    }
             }
         }
         s0 = row16_sum(s0);  // a unit's 16 lanes are one DPP row of the wave

@@ -45,6 +45,24 @@ def _same(a, b):
     assert np.array_equal(a[2].view(np.int64), b[2].view(np.int64))  # bitwise
 
 
+def test_assemble_head_segmented_reduce_example(dev):
+    """The paper's warp-segmented reduction example (Sec. 6.2; the values and
+    sums in tests/golden), in list order and shuffled."""
+    import json
+    import os
+
+    _say("assemble segmented-reduce example")
+    with open(os.path.join(os.path.dirname(__file__), "golden", "head_segmented_reduce_example.json")) as fh:
+        g = json.load(fh)
+    seg = np.cumsum(g["tags"]) - 1
+    blocks = np.asarray(g["values"], dtype=np.float64)[:, None, None] * np.ones((1, 3, 3))
+    n = len(g["segment_sums"])
+    for perm in (np.arange(seg.size), np.random.default_rng(3).permutation(seg.size)):
+        got = _gpu(n, seg[perm], np.zeros(seg.size, np.int64), blocks[perm], dev)
+        assert list(got[2][:, 0, 0]) == g["segment_sums"]
+        _same(got, oracle.assemble(n, seg[perm], np.zeros(seg.size, np.int64), blocks[perm]))
+
+
 @pytest.mark.parametrize("n,m,seed", [(7, 50, 0), (300, 20000, 1), (2000, 150000, 2)])
 def test_assemble_random_lists(dev, n, m, seed):
     _say("assemble random", n, m)

@@ -253,6 +253,28 @@ def test_hierarchy_rebuild_level_cap(dev, max_levels):
     _check_rebuild(units, sn, P)
 
 
+def test_hierarchy_rebuild_after_build(dev):
+    """After mas_build the rebuild reads the partition's map from the
+    solver's workspace; the result is the same, and a solve on the analysed
+    pattern still works afterwards."""
+    from paper_2411_06224_amd import BlockMatrix, MasPcg
+
+    _say("hierarchy rebuild after build")
+    s, n_pairs = REBUILD_CASES["contact6_300"]()
+    rp1, ci1 = _graph_pattern(s)
+    rp2, ci2, val2 = _add_pairs(rp1, ci1, n_pairs, seed=16)
+    val1 = np.where((np.repeat(np.arange(s.n), np.diff(rp1)) == ci1)[:, None, None], 10.0, 0.01) * np.eye(3)[None]
+    S = MasPcg(rp1, ci1, graph=(s.gptr, s.gadj), domain_size=16)
+    H1 = BlockMatrix.from_numpy(rp1, ci1, val1, device=dev)
+    S.build(H1)
+    P = oracle.MAS(rp2, ci2, val2, N=16, gptr=s.gptr, gadj=s.gadj)
+    units, sn = S.hierarchy_rebuild(torch.as_tensor(rp2, device=dev), torch.as_tensor(ci2, device=dev))
+    _check_rebuild(units, sn, P)
+    b = torch.ones(3 * s.n, dtype=torch.float64, device=dev)
+    x, res = S.solve(H1, b, tol=1e-10)
+    assert res["status"] == 0 and res["true_rel_residual"] <= 1e-10
+
+
 def test_hierarchy_rebuild_deep(dev):
     """A pattern whose hierarchy reaches the level limit (16 levels)."""
     from paper_2411_06224_amd import MasPcg

@@ -477,6 +477,20 @@ def test_assemble_integer_blocks_match_dense_accumulation():
     assert np.array_equal(got, dense)
 
 
+def test_assemble_head_segmented_reduce_example():
+    """The paper's warp-segmented reduction example (tests/golden): listed
+    blocks whose keys start a new segment where the tag is 1 reduce to the
+    printed segment sums, and the same list shuffled gives the same."""
+    g = _golden("head_segmented_reduce_example.json")
+    seg = np.cumsum(g["tags"]) - 1
+    blocks = np.asarray(g["values"], dtype=np.float64)[:, None, None] * np.ones((1, 3, 3))
+    rp, ci, val = oracle.assemble(len(g["segment_sums"]), seg, np.zeros_like(seg), blocks)
+    assert list(val[:, 0, 0]) == g["segment_sums"] and np.all(val == val[:, :1, :1])
+    perm = np.random.default_rng(3).permutation(seg.size)
+    _, _, val2 = oracle.assemble(len(g["segment_sums"]), seg[perm], np.zeros_like(seg), blocks[perm])
+    assert np.array_equal(val2, val)
+
+
 def test_assemble_sums_in_list_order_and_edge_cases():
     big = np.full((3, 3), 1e16)
     one = np.ones((3, 3))
