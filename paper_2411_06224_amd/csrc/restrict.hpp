@@ -30,32 +30,39 @@ struct GroupUnits {
 };
 
 // Plan entries a thread holds in registers: thread t takes component t % 3
-// of the group's level-1 unit t / 3 and of its level >= 2 writer t / 3
-// (the common case, restrict_fast_ok; else the entries are loaded where
-// they are used).
+// of the group's level-1 unit t / 3 and, in pass p < kWP of the writers of
+// levels >= 2, of writer (t + p blockDim) / 3 (the common case,
+// restrict_fast_ok, needs one pass; entries of later passes are loaded
+// where they are used).
+template <int kWP = 1>
 struct RestrictLoads {
     GroupUnits gu;
-    int u1_slot;      // lowest slot of the thread's level-1 unit (-1 pad)
-    uint64_t u1_mask; // lanes of its domain in that unit
-    int w_pos, w_li;  // the thread's writer: partial position (-1 pad), table entry
-    uint64_t w_mask;  // the writer's members among the group's level-1 units
+    int u1_slot;          // lowest slot of the thread's level-1 unit (-1 pad)
+    uint64_t u1_mask;     // lanes of its domain in that unit
+    int w_pos[kWP];       // the thread's writers: partial position (-1 pad), table entry
+    int w_li[kWP];
+    uint64_t w_mask[kWP]; // the writer's members among the group's level-1 units
 };
 
 // Issues the loads of the group's plan, all at once and unconditionally (at
 // clamped indices), so that no branch separates them from the loads issued
 // before them and a wait for those need not wait for these too.
-__device__ inline RestrictLoads restrict_load(const SolverView& v, int g) {
-    RestrictLoads R;
+template <int kWP = 1>
+__device__ inline RestrictLoads<kWP> restrict_load(const SolverView& v, int g) {
+    RestrictLoads<kWP> R;
     const int t = threadIdx.x;
     const int u1_lo = v.g_u1[g];
     R.gu = v.L >= 2 ? GroupUnits{u1_lo, v.g_u1[g + 1] - u1_lo} : GroupUnits{0, 0};
     const long long i1 = static_cast<long long>(g) * v.W1 + min(t / 3, v.W1 - 1);
     R.u1_slot = v.gu1_slot[i1];
     R.u1_mask = v.gu1_mask[i1];
-    const long long iw = static_cast<long long>(g) * v.GW + min(t / 3, v.GW - 1);
-    R.w_pos = v.gw_pos[iw];
-    R.w_li = v.gw_li[iw];
-    R.w_mask = v.gw_mask[iw];
+#pragma unroll
+    for (int p = 0; p < kWP; ++p) {
+        const long long iw = static_cast<long long>(g) * v.GW + min((t + p * static_cast<int>(blockDim.x)) / 3, v.GW - 1);
+        R.w_pos[p] = v.gw_pos[iw];
+        R.w_li[p] = v.gw_li[iw];
+        R.w_mask[p] = v.gw_mask[iw];
+    }
     return R;
 }
 
@@ -64,8 +71,11 @@ __device__ inline RestrictLoads restrict_load(const SolverView& v, int g) {
 // for nothing.  Loads and stores share one counter, and after a loop whose
 // loads the compiler cannot count, a first use of an early-loaded register
 // waits for every outstanding access -- the stores just issued included.
-__device__ __forceinline__ void restrict_ready(const RestrictLoads& R) {
-    asm volatile("" ::"v"(R.u1_slot), "v"(R.u1_mask), "v"(R.w_pos), "v"(R.w_li), "v"(R.w_mask));
+template <int kWP>
+__device__ __forceinline__ void restrict_ready(const RestrictLoads<kWP>& R) {
+    asm volatile("" ::"v"(R.u1_slot), "v"(R.u1_mask));
+#pragma unroll
+    for (int p = 0; p < kWP; ++p) asm volatile("" ::"v"(R.w_pos[p]), "v"(R.w_li[p]), "v"(R.w_mask[p]));
 }
 
 // sum over the members m < n of mask, in ascending m, of x[3 m] (x in shared
@@ -101,8 +111,8 @@ __host__ __device__ inline bool restrict_fast_ok(int W1, int GW, int threads) {
     return W1 <= 64 && 3 * W1 <= threads && 3 * GW <= threads;
 }
 
-template <bool kFast = false>
-__device__ inline void restrict_group(const SolverView& v, int g, const RestrictLoads& R, const double* rs,
+template <bool kFast = false, int kWP = 1>
+__device__ inline void restrict_group(const SolverView& v, int g, const RestrictLoads<kWP>& R, const double* rs,
                                       double* sm, double* __restrict__ out1, double* __restrict__ outpart) {
     if (v.L < 2) return;
     const int t = threadIdx.x, N = v.N;
@@ -126,42 +136,52 @@ __device__ inline void restrict_group(const SolverView& v, int g, const Restrict
     }
     if (v.L <= 2) return;
     __syncthreads();
-    // one thread per (writer of levels >= 2, component)
-    for (int o = t; o < 3 * v.GW; o += blockDim.x) {
+    // one thread per (writer of levels >= 2, component): the first kWP
+    // passes from the preloaded entries, later ones (not in the fast case)
+    // load theirs; a group's writers come first in its table, then pads, so
+    // a thread stops at its first pad
+    auto write = [&](int e, int c, int pos, int li, uint64_t m) {
+        double s2;
+        if (kFast || v.W1 <= 64) {
+            s2 = masked_sum_tree(r1s + c, m, n1);
+        } else {  // more level-1 units in the group than mask bits: compare ancestors
+            const int* anc = v.ganc + static_cast<long long>(g) * (v.L - 2) * v.W1 + (li / v.W1) * v.W1;
+            const int a = anc[li % v.W1];
+            s2 = 0.0;
+            for (int j = 0; j < n1; ++j)
+                if (anc[j] == a) s2 += r1s[3 * j + c];
+        }
+        (void)e;
+        outpart[3 * pos + c] = s2;
+    };
+    int o = t;
+#pragma unroll
+    for (int p = 0; p < kWP; ++p) {
+        if (o >= 3 * v.GW) return;
         const int e = o / 3, c = o - 3 * e;
-        int pos = R.w_pos, li = R.w_li;
-        uint64_t m = R.w_mask;
-        if (!kFast && o != t) {
-            const long long k = static_cast<long long>(g) * v.GW + e;
-            pos = v.gw_pos[k];
-            li = v.gw_li[k];
-            m = v.gw_mask[k];
-        }
-        if (pos >= 0) {
-            double s2;
-            if (kFast || v.W1 <= 64) {
-                s2 = masked_sum_tree(r1s + c, m, n1);
-            } else {  // more level-1 units in the group than mask bits: compare ancestors
-                const int* anc = v.ganc + static_cast<long long>(g) * (v.L - 2) * v.W1 + (li / v.W1) * v.W1;
-                const int a = anc[li % v.W1];
-                s2 = 0.0;
-                for (int j = 0; j < n1; ++j)
-                    if (anc[j] == a) s2 += r1s[3 * j + c];
-            }
-            outpart[3 * pos + c] = s2;
-        }
-        if (kFast) break;
+        if (R.w_pos[p] < 0) return;
+        write(e, c, R.w_pos[p], R.w_li[p], R.w_mask[p]);
+        if (kFast) return;
+        o += blockDim.x;
+    }
+    for (; o < 3 * v.GW; o += blockDim.x) {
+        const int e = o / 3, c = o - 3 * e;
+        const long long k = static_cast<long long>(g) * v.GW + e;
+        const int pos = v.gw_pos[k];
+        if (pos < 0) return;
+        write(e, c, pos, v.gw_li[k], v.gw_mask[k]);
     }
 }
 
 // restrict_group with the fast path when the host found it applicable
 // (v.rfast: tables that fit blocks of 256 threads and more).
-__device__ inline void restrict_group_any(const SolverView& v, int g, const RestrictLoads& R, const double* rs,
+template <int kWP>
+__device__ inline void restrict_group_any(const SolverView& v, int g, const RestrictLoads<kWP>& R, const double* rs,
                                           double* sm, double* __restrict__ out1, double* __restrict__ outpart) {
     if (v.rfast)
-        restrict_group<true>(v, g, R, rs, sm, out1, outpart);
+        restrict_group<true, kWP>(v, g, R, rs, sm, out1, outpart);
     else
-        restrict_group<false>(v, g, R, rs, sm, out1, outpart);
+        restrict_group<false, kWP>(v, g, R, rs, sm, out1, outpart);
 }
 
 }  // namespace maspcg

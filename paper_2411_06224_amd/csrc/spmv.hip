@@ -316,7 +316,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_user(int n_rows, const int* _
 // they hold it, spmv_restrict_capacity).
 template <int kRQ>
 __device__ __forceinline__ void finish_pq(const SolverView& v, int g, int nown, int r0, const double (&acc)[2],
-                                          const double (&pv)[2], double* prod, double* buf, const RestrictLoads& pl) {
+                                          const double (&pv)[2], double* prod, double* buf, const RestrictLoads<>& pl) {
     const int t = threadIdx.x;
     if constexpr (kRQ) restrict_ready(pl);
     double part = 0.0;
@@ -376,7 +376,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq(SolverView v, const T* __r
         po[q] = pold[e];
     }
     const ChunkCols c0 = chunk_cols(v.ci0, v.rp0[r0], v.rp0[r1]);
-    RestrictLoads pl{};
+    RestrictLoads<> pl{};
     if constexpr (kRQ) pl = restrict_load(v, g);
     const int stop = v.st->done;
     keep_loads_issued();
@@ -440,7 +440,7 @@ __global__ void __launch_bounds__(kThreads) k_spmv_pq_sym(SolverView v, const T*
 #pragma unroll
     for (int j = 0; j < kTlRegs; ++j) tlr[j] = tsrc[min(t + j * kThreads, max(tn - 1, 0))];
     const SymCols c0 = sym_cols(v, v.srp[r0], v.srp[r1]);
-    RestrictLoads pl{};
+    RestrictLoads<> pl{};
     if constexpr (kRQ) pl = restrict_load(v, g);
     const int stop = v.st->done;
     keep_loads_issued();
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(SolverView v, double* __r
     const int g = spmv_group(v);
     const int r0 = g * v.RG, r1 = min(r0 + v.RG, v.NS);
     double acc[2];
-    const RestrictLoads pl = restrict_load(v, g);
+    const RestrictLoads<> pl = restrict_load(v, g);
     if constexpr (kSym) {
         double* xs = dyn + 3 * v.RG + restrict_smem_doubles(v.RG, v.W1, v.L);
         int* tl = reinterpret_cast<int*>(xs + 3 * v.RG);

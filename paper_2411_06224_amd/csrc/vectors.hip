@@ -90,7 +90,7 @@ __global__ void k_init_rhs(SolverView v) {
     double bv = 0.0;
     const bool own = t < 3 * v.RG && i < 3LL * v.NS;
     if (own) bv = v.b[i];
-    const RestrictLoads pl = restrict_load(v, g);
+    const RestrictLoads<> pl = restrict_load<>(v, g);
     restrict_ready(pl);
     if (own) {
         v.r[i] = bv;
@@ -109,6 +109,11 @@ __global__ void k_init_rhs(SolverView v) {
 // partials, rho_{k-1} as the SpMV of this iteration recorded it), x += alpha p,
 // r -= alpha q, the partial of ||r||^2 and the restriction of the new
 // residual.  sigma <= 0 stops the solve (NOT_SPD).
+// Writer passes of the restriction whose plan entries k_update loads with
+// its other early loads (systems whose groups write many coarse partials,
+// such as affine bodies carried through many levels, take several passes).
+constexpr int kUpdatePasses = 4;
+
 __global__ void k_update(SolverView v, int k) {
     extern __shared__ double sm[];
     double* rs = sm;
@@ -124,7 +129,7 @@ __global__ void k_update(SolverView v, int k) {
     const long long ic = own ? i : 0;  // unconditional loads (see partials_load)
     const double* pk = v.p[k & 1];
     const double xv = v.x[ic], pv = pk[ic], rv0 = v.r[ic], qv = v.q[ic];
-    const RestrictLoads pl = restrict_load(v, g);
+    const RestrictLoads<kUpdatePasses> pl = restrict_load<kUpdatePasses>(v, g);
     const int stop = v.st->done;
     keep_loads_issued();
     if (stop) return;
@@ -160,7 +165,7 @@ __global__ void k_restrict(SolverView v) {
     const int g = xcd_group(blockIdx.x, v.G), t = threadIdx.x;
     const long long i = 3LL * g * v.RG + t;
     const double rv = (t < 3 * v.RG && i < 3LL * v.NS) ? v.r[i] : 0.0;
-    const RestrictLoads pl = restrict_load(v, g);
+    const RestrictLoads<> pl = restrict_load<>(v, g);
     if (t < 3 * v.RG) rs[t] = rv;
     __syncthreads();
     restrict_group_any(v, g, pl, rs, sm + 3 * v.RG, v.r1, v.cpart);
