@@ -184,3 +184,55 @@ def test_abd_contact_blocks_edges():
     assert torch.equal(b.cpu(), want)
     assert r.cpu().tolist() == [5 + a for a in range(4) for _ in range(4)]
     assert c.cpu().tolist() == [5 + bb for _ in range(4) for bb in range(4)]
+
+
+@pytest.mark.gpu
+def test_contact_system_assembled_and_solved():
+    """The step before the solve, end to end on a small membrane with bodies:
+    the system's own blocks plus the two-level-reduced contact blocks,
+    assembled on the GPU (bit-exact with the oracle's assembly of the same
+    lists), then analysed and solved with the MAS-PCG; the solution agrees
+    with the oracle's PCG on the same matrix."""
+    import torch
+    import paper_2411_06224_amd as mp
+    from synth import membrane_system
+
+    s = membrane_system(16, 6, seed=5)
+    d = body_contacts(cells=16, n_bodies=6, n_vf=300, n_ee=60, seed=6)
+    assert d["n_dof_rows"] == s.n
+    dev = torch.device("cuda:0")
+    t = _device_inputs(d, torch)
+    r2, c2, b2 = mp.abd_contact_blocks(d["n_nodes"], t["node_row"], t["node_is_body"], t["node_xbar"], t["rows"],
+                                       t["cols"], t["blocks"], levels=2)
+    mr = np.repeat(np.arange(s.n, dtype=np.int32), np.diff(s.row_ptr))
+    mc = s.col_idx.astype(np.int32)
+    rows = torch.cat([torch.as_tensor(mr, device=dev), r2])
+    cols = torch.cat([torch.as_tensor(mc, device=dev), c2])
+    blocks = torch.cat([torch.as_tensor(s.val.reshape(-1, 3, 3), device=dev), b2])
+    Hg = mp.bcsr_assemble(s.n, rows, cols, blocks)
+    o2 = _oracle_two_level(d)
+    rp, ci, val = oracle.assemble(s.n, np.concatenate([mr, o2[0]]), np.concatenate([mc, o2[1]]),
+                                  np.concatenate([s.val.reshape(-1, 3, 3), o2[2]]))
+    assert np.array_equal(Hg.row_ptr.cpu().numpy(), rp) and np.array_equal(Hg.col_idx.cpu().numpy(), ci)
+    assert np.array_equal(Hg.val.cpu().numpy().view(np.int64), val.view(np.int64))
+    assert ci.size > s.col_idx.size  # the contacts added blocks
+    S = mp.MasPcg(rp, ci, graph=(s.gptr, s.gadj), domain_size=16)
+    b = torch.as_tensor(s.b, device=dev)
+    S.build(Hg)
+    P = oracle.MAS(rp, ci, val, N=16, gptr=s.gptr, gadj=s.gadj)
+    # ten iterations against the oracle's ten (the parity contract of the
+    # fixed-iteration tests), then a converged solve
+    xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+    x, res = S.solve(Hg, b, tol=0.0, max_iter=10)
+    assert res["iterations"] == it == 10
+    assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+    # converged: the count contract of the other converged tests (the
+    # oracle's spread under rounding-level changes, +-2) and x against it
+    from count_contract import oracle_ensemble
+
+    lo, hi, x_tol, x_ref, _ = oracle_ensemble(lambda: oracle.MAS(rp, ci, val, N=16, gptr=s.gptr, gadj=s.gadj),
+                                              s.b, 1e-10)
+    x, res = S.solve(Hg, b, tol=1e-10)
+    assert res["status"] == 0 and res["true_rel_residual"] <= 1e-10
+    assert lo <= res["iterations"] <= hi
+    assert np.linalg.norm(x.cpu().numpy() - x_ref) <= x_tol * np.linalg.norm(x_ref)
