@@ -81,14 +81,15 @@ __global__ void __launch_bounds__(256) k_coarse_sum_next(int nnzA, int nnzPrev, 
 }
 
 // ------------------------------------------------------- domain inversion
-// One 64-lane wave per domain (all levels in one launch).  The domain
-// matrix (3N x 3N, padded to 16T with identity rows on empty lanes so that
-// the inverse of the occupied part comes out directly) sits in LDS and is
-// inverted in place by block Gauss-Jordan over 16x16 tiles:
-//   P = inv(A_kk) (register-resident scalar Gauss-Jordan, 16 pivots),
+// One workgroup of four waves per domain (all levels in one launch).  The
+// domain matrix (3N x 3N, padded to 16T with identity rows on empty lanes so
+// that the inverse of the occupied part comes out directly) sits in LDS and
+// is inverted in place by block Gauss-Jordan over 16x16 tiles:
+//   P = inv(A_kk) (register-resident scalar Gauss-Jordan, 16 pivots, wave 0),
 //   A_kj <- P A_kj, A_ij <- A_ij - A_ik A_kj, A_ik <- -A_ik P, A_kk <- P,
-// with the tile products on v_mfma_f64_16x16x4f64.  Pivots are Schur
-// complement diagonals of an SPD matrix; a pivot <= 0 flags NOT_SPD.
+// with the tile products on v_mfma_f64_16x16x4f64, the tiles of each phase
+// dealt round-robin to the four waves.  Pivots are Schur complement
+// diagonals of an SPD matrix; a pivot <= 0 flags NOT_SPD.
 //
 // MFMA f64 16x16x4 lane layout on gfx950: lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; result register v of lane l is D[l / 16 + 4 v][l % 16].
@@ -103,22 +104,27 @@ __device__ __forceinline__ int level_of(const DomTable& tab, int L, int g) {
     return l;
 }
 
+constexpr int kInvWaves = 4;
+constexpr int kInvThreads = 64 * kInvWaves;
+
 template <int T>
-__global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __restrict__ Hu, int want32, DomTable tab) {
+__global__ void __launch_bounds__(kInvThreads) k_invert(BuildView B, const double* __restrict__ Hu, int want32,
+                                                        DomTable tab) {
     constexpr int NP = 16 * T;
     constexpr int LD = NP + 1;  // odd stride: a 16-row column read hits 16 distinct bank pairs
     __shared__ double A[NP * LD];
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index, uniform in the wave
     const int l = level_of(tab, B.L, blockIdx.x);
     const int d = blockIdx.x - tab.off[l];
     const int N = B.N, n = 3 * N;
 
-    for (int e = lane; e < NP * LD; e += 64) A[e] = 0.0;
+    for (int e = tid; e < NP * LD; e += kInvThreads) A[e] = 0.0;
     __syncthreads();
 
     // gather the upper in-domain blocks and mirror them
     const int* dptr = B.dom_ptr[l];
-    for (int q = dptr[d] + lane; q < dptr[d + 1]; q += 64) {
+    for (int q = dptr[d] + tid; q < dptr[d + 1]; q += kInvThreads) {
         const int k = B.dom_blk[l][q];
         const int ab = B.dom_ab[l][q];
         const int a = ab & 255, b = ab >> 8;
@@ -148,7 +154,7 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
                 }
         }
     }
-    // occupied lanes of this domain as a bit mask
+    // occupied lanes of this domain as a bit mask (every wave forms the same)
     bool occ_lane = false;
     if (lane < N) {
         const int u = d * N + lane;
@@ -156,7 +162,7 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
     }
     const unsigned long long occ = __ballot(occ_lane);
     __syncthreads();
-    for (int p = lane; p < NP; p += 64) {
+    for (int p = tid; p < NP; p += kInvThreads) {
         const bool live = p < n && ((occ >> (p / 3)) & 1ull);
         if (!live) A[p * LD + p] = 1.0;
     }
@@ -167,37 +173,39 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
 #pragma unroll
     for (int k = 0; k < T; ++k) {
         const int base = 16 * k;
-        // ---- P = inv(A_kk): lane holds column c16, rows 4 g4 + v
-        double a[4];
+        // ---- P = inv(A_kk) by wave 0: lane holds column c16, rows 4 g4 + v
+        if (w == 0) {
+            double a[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) a[v] = A[(base + 4 * g4 + v) * LD + base + c16];
+            for (int v = 0; v < 4; ++v) a[v] = A[(base + 4 * g4 + v) * LD + base + c16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int jg = j >> 2, jv = j & 3;
-            const double aj = a[jv];
-            const double piv = __shfl(aj, jg * 16 + j);
-            const double rowj = __shfl(aj, jg * 16 + c16);
-            double colj[4];
+            for (int j = 0; j < 16; ++j) {
+                const int jg = j >> 2, jv = j & 3;
+                const double aj = a[jv];
+                const double piv = __shfl(aj, jg * 16 + j);
+                const double rowj = __shfl(aj, jg * 16 + c16);
+                double colj[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) colj[v] = __shfl(a[v], g4 * 16 + j);
-            ok = ok && (piv > 0.0) && finite(piv);
-            const double inv = 1.0 / piv;
+                for (int v = 0; v < 4; ++v) colj[v] = __shfl(a[v], g4 * 16 + j);
+                ok = ok && (piv > 0.0) && finite(piv);
+                const double inv = 1.0 / piv;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 4 * g4 + v;
-                if (i == j)
-                    a[v] = (c16 == j) ? inv : a[v] * inv;
-                else
-                    a[v] = (c16 == j) ? -colj[v] * inv : a[v] - colj[v] * rowj * inv;
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 4 * g4 + v;
+                    if (i == j)
+                        a[v] = (c16 == j) ? inv : a[v] * inv;
+                    else
+                        a[v] = (c16 == j) ? -colj[v] * inv : a[v] - colj[v] * rowj * inv;
+                }
             }
-        }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) A[(base + 4 * g4 + v) * LD + base + c16] = a[v];
+            for (int v = 0; v < 4; ++v) A[(base + 4 * g4 + v) * LD + base + c16] = a[v];
+        }
         __syncthreads();
-        // ---- row panel: A_kj <- P A_kj
+        // ---- row panel: A_kj <- P A_kj, tile j (j != k) to wave (its rank) % 4
 #pragma unroll
         for (int j = 0; j < T; ++j) {
-            if (j == k) continue;
+            if (j == k || (j - (j > k)) % kInvWaves != w) continue;
             v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
@@ -209,13 +217,13 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
             for (int v = 0; v < 4; ++v) A[(base + g4 + 4 * v) * LD + 16 * j + c16] = acc[v];
         }
         __syncthreads();
-        // ---- trailing update: A_ij <- A_ij - A_ik A_kj
+        // ---- trailing update: A_ij <- A_ij - A_ik A_kj, tile (i, j) to wave (its rank) % 4
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             if (i == k) continue;
 #pragma unroll
             for (int j = 0; j < T; ++j) {
-                if (j == k) continue;
+                if (j == k || ((i - (i > k)) * (T - 1) + (j - (j > k))) % kInvWaves != w) continue;
                 v4d acc;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[v] = A[(16 * i + g4 + 4 * v) * LD + 16 * j + c16];
@@ -230,10 +238,11 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
             }
         }
         __syncthreads();
-        // ---- column panel: A_ik <- -A_ik P
+        // ---- column panel: A_ik <- -A_ik P, tile i (i != k) to wave (its rank) % 4;
+        // a tile's wave reads it whole before writing it (one wave, in order)
 #pragma unroll
         for (int i = 0; i < T; ++i) {
-            if (i == k) continue;
+            if (i == k || (i - (i > k)) % kInvWaves != w) continue;
             v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
@@ -241,20 +250,19 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
                 const double bv = A[(base + 4 * kk + g4) * LD + base + c16];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
             }
-            __syncthreads();
 #pragma unroll
             for (int v = 0; v < 4; ++v) A[(16 * i + g4 + 4 * v) * LD + base + c16] = acc[v];
         }
         __syncthreads();
     }
-    if (!ok && lane == 0) atomicOr(B.flag, 1);
+    if (w == 0 && !ok && lane == 0) atomicOr(B.flag, 1);
 
     const bool packed = l == 0 && B.packed0;
     if (packed) {
         // FP64: symmetric-packed lower triangle (the mean of the two
         // triangles of the computed inverse), zero on empty lanes
         double* o64 = B.inv64[0] + (long long)d * kPacked;
-        for (int j = 0; j < kPackedN; ++j)
+        for (int j = w; j < kPackedN; j += kInvWaves)  // column j (rows j..47) by wave j % 4
             for (int i = j + lane; i < kPackedN; i += 64) {
                 const bool live = ((occ >> (i / 3)) & 1ull) && ((occ >> (j / 3)) & 1ull);
                 o64[packed_col(j) + i - j] = live ? 0.5 * (A[i * LD + j] + A[j * LD + i]) : 0.0;
@@ -265,7 +273,7 @@ __global__ void __launch_bounds__(64) k_invert(BuildView B, const double* __rest
     double* o64 = packed ? nullptr : B.inv64[l] + off;
     float* o32 = want32 ? B.inv32[l] + off : nullptr;
     if (o64 || o32)
-        for (int e = lane; e < n * n; e += 64) {
+        for (int e = tid; e < n * n; e += kInvThreads) {
             const int col = e / n, row = e - col * n;
             const bool live = ((occ >> (row / 3)) & 1ull) && ((occ >> (col / 3)) & 1ull);
             const double val = live ? A[row * LD + col] : 0.0;
@@ -807,7 +815,7 @@ DomTable make_table(const int* ndom, int first, int L) {
 
 template <int T>
 void launch_invert_t(const BuildView& b, const double* Hu, bool want32, int total, const DomTable& tab, hipStream_t s) {
-    launch_kernel(k_invert<T>, dim3(total), dim3(64), 0, s, b, Hu, want32 ? 1 : 0, tab);
+    launch_kernel(k_invert<T>, dim3(total), dim3(kInvThreads), 0, s, b, Hu, want32 ? 1 : 0, tab);
 }
 
 }  // namespace

@@ -580,7 +580,7 @@ def test_pcg_dot_modes():
                      xr.ctypes.data_as(oracle._pd), 1e-10, 10000, ctypes.byref(it), ctypes.byref(rr), ctypes.byref(tr))
     assert st == st0 == oracle.OK and it.value == it0
     assert np.array_equal(xr.view(np.uint64), x0.view(np.uint64))
-    # compensated dots: same solution up to the tolerance, Cholesky as the judge
+    # compensated dots: same solution up to the tolerance, Cholesky as the reference
     x1, st1, it1, *_ = P.pcg(s.b, tol=1e-10, dots=oracle.DOT_COMPENSATED)
     H = sparse_dense(s)
     xs = sla.cho_solve(sla.cho_factor(H), s.b)
