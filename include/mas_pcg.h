@@ -360,7 +360,8 @@ int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t
  *   workspace: device scratch, ws_bytes >= mas_hierarchy_workspace_size,
  *       256-byte aligned (not shared with a running call).
  * The node -> slot map of the analysis is read from the solver's workspace
- * once mas_build has placed the plans there (nothing is copied); before the
+ * once mas_build has placed the plans there (nothing is copied; that
+ * workspace must then still be allocated and unchanged); before the
  * first mas_build it is copied from the handle into this workspace on each
  * call.  Does not synchronise the stream.  Errors:
  * MAS_NOT_READY, MAS_INVALID_ARG, MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
