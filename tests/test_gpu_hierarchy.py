@@ -302,3 +302,25 @@ def test_hierarchy_rebuild_rejects_out_of_range_columns(dev):
     rp[-1] = rp[-1] + 7  # row range past the column list
     units, _ = S.hierarchy_rebuild(torch.as_tensor(rp, device=dev), torch.as_tensor(s.col_idx, device=dev))
     assert int(units[0]) == -1
+
+
+def test_hierarchy_rebuild_diagonal_only_pattern(dev):
+    """A pattern without off-diagonal blocks merges nothing: one level, every
+    node its own level-0 unit (its slot)."""
+    from paper_2411_06224_amd import MasPcg
+
+    _say("hierarchy rebuild diagonal-only pattern")
+    s = cube(4, E=1e6, nu=0.49, seed=3, n_contacts=0)
+    S = MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16)
+    n = s.n
+    rp = torch.arange(n + 1, dtype=torch.int32, device=dev)
+    ci = torch.arange(n, dtype=torch.int32, device=dev)
+    units, sn = S.hierarchy_rebuild(rp, ci)
+    u = units.cpu().numpy()
+    mp_, _, _ = S.ordering()
+    assert u[0] == 1 and u[1] == S.info()["units"][0] and np.all(u[2:] == 0)
+    assert np.array_equal(sn.cpu().numpy()[0], mp_) and np.all(sn.cpu().numpy()[1:] == -1)
+    # no blocks at all (row_ptr of zeros): the same
+    units, sn = S.hierarchy_rebuild(torch.zeros(n + 1, dtype=torch.int32, device=dev),
+                                    torch.zeros(0, dtype=torch.int32, device=dev))
+    assert int(units[0]) == 1 and np.array_equal(sn.cpu().numpy()[0], mp_)
