@@ -189,7 +189,7 @@ size_t abd_contact_workspace_size(int32_t n_nodes, int64_t m);
  *              256-byte aligned.
  * node_row entries are not checked here (the DOF rows they produce are, by
  * bcsr_assemble).
- * Limits: n_nodes + 1 <= 2^20, 16 m < 2^31.  Synchronises the stream.
+ * Limits: n_nodes < 2^31 - 1, 16 m < 2^31.  Synchronises the stream.
  * Errors: MAS_INVALID_ARG (an index out of range, n_out > capacity: then
  * nothing is written), MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
 int abd_contact_blocks(int32_t n_nodes, const int32_t* node_row, const int32_t* node_is_body,
@@ -289,7 +289,9 @@ size_t bcsr_assemble_workspace_size(int32_t n_rows, int64_t n_in);
  *         exceeds capacity, so the caller can size the outputs).
  *   workspace: device scratch of ws_bytes >= bcsr_assemble_workspace_size,
  *              256-byte aligned.
- * Limits: n_in < 2^31, n_rows + 1 <= 2^20.  Synchronises the stream.
+ * Limits: n_in < 2^31, n_rows < 2^31 - 1 (the sort runs over 2 ceil(log2
+ * (n_rows + 1)) key bits: 34 for a 110,592-row system).  Synchronises the
+ * stream.
  * Errors: MAS_INVALID_ARG (an index out of range, a limit exceeded,
  * nnzb > capacity: then col_idx and val are not written),
  * MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */

@@ -761,7 +761,7 @@ int assemble_impl(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32
 
 bool assemble_args_ok(int32_t n_rows, int64_t n_in, const int32_t* rows, const int32_t* cols, const double* blocks,
                       int32_t* row_ptr, int64_t capacity, int64_t* nnzb) {
-    if (n_rows < 1 || n_rows + 1 > (1 << 20) || n_in < 0 || n_in > 0x7fffffffLL || capacity < 0 || !nnzb ||
+    if (n_rows < 1 || n_rows > 0x7ffffffe || n_in < 0 || n_in > 0x7fffffffLL || capacity < 0 || !nnzb ||
         !row_ptr)
         return false;
     return n_in == 0 || (rows && cols && blocks);
@@ -820,7 +820,7 @@ int abd_contact_blocks(int32_t n_nodes, const int32_t* node_row, const int32_t* 
                        const double* node_xbar, int64_t m, const int32_t* r, const int32_t* c, const double* C,
                        int32_t levels, int32_t* out_rows, int32_t* out_cols, double* out_blocks, int64_t capacity,
                        int64_t* n_out, void* workspace, size_t ws_bytes, void* stream) {
-    if (n_nodes < 1 || n_nodes + 1 > (1 << 20) || m < 0 || m > 0x7fffffffLL / 16 || capacity < 0 || !n_out ||
+    if (n_nodes < 1 || n_nodes > 0x7ffffffe || m < 0 || m > 0x7fffffffLL / 16 || capacity < 0 || !n_out ||
         !node_row || !node_is_body || !node_xbar || !workspace || (levels != 1 && levels != 2))
         return MAS_INVALID_ARG;
     if (m > 0 && (!r || !c || !C)) return MAS_INVALID_ARG;

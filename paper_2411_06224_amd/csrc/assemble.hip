@@ -2,7 +2,8 @@
 // reduction of Sec. 6.2 computes: the blocks of equal (row, col) key meet
 // contiguously after sorting by key and are reduced segment by segment).
 //
-// Each listed block gets the key (row << 20) | col; a stable radix sort of
+// Each listed block gets the key (row << cb) | col, cb the bit width of the
+// largest index (n_rows < 2^cb); a stable radix sort of
 // (key, list position) pairs (rocPRIM) places equal keys together in list
 // order; segment heads and their exclusive scan number the distinct blocks;
 // each distinct block is summed over its segment in list order, nine
@@ -21,7 +22,6 @@ namespace {
 constexpr int kAsmThreads = 256;
 constexpr int kAsmBatch = 4;  // listed blocks loaded together by the segment sums
 constexpr int kScanItems = 1024;  // elements per block of the scan
-constexpr int kKeyBits = 40;      // row and column below 2^20 each
 
 __global__ void k_fill_int(int* __restrict__ p, long long n, int value) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -94,15 +94,18 @@ __global__ void k_scan_add(int* __restrict__ out, int n, const int* __restrict__
 
 // Key and list position of every listed block; an index out of range
 // raises flag bit 0 (its key sorts last and is never reduced).
-__global__ void __launch_bounds__(kAsmThreads) k_asm_keys(long long n_in, int n_rows, const int* __restrict__ rows,
-                                                          const int* __restrict__ cols, uint64_t* __restrict__ key,
-                                                          int* __restrict__ pos, int* __restrict__ flag) {
+__device__ __forceinline__ uint64_t key_sentinel(int cb) { return (1ull << (2 * cb)) - 1; }  // above every valid key
+
+__global__ void __launch_bounds__(kAsmThreads) k_asm_keys(long long n_in, int n_rows, int cb,
+                                                          const int* __restrict__ rows, const int* __restrict__ cols,
+                                                          uint64_t* __restrict__ key, int* __restrict__ pos,
+                                                          int* __restrict__ flag) {
     const long long k = static_cast<long long>(blockIdx.x) * kAsmThreads + threadIdx.x;
     if (k >= n_in) return;
     const int r = rows[k], c = cols[k];
     const bool bad = r < 0 || r >= n_rows || c < 0 || c >= n_rows;
     if (bad) atomicOr(flag, 1);
-    key[k] = bad ? (1ull << kKeyBits) - 1 : (static_cast<uint64_t>(r) << 20) | static_cast<uint64_t>(c);
+    key[k] = bad ? key_sentinel(cb) : (static_cast<uint64_t>(r) << cb) | static_cast<uint64_t>(c);
     pos[k] = static_cast<int>(k);
 }
 
@@ -115,7 +118,8 @@ __global__ void __launch_bounds__(kAsmThreads) k_asm_heads(long long n_in, const
 // Segment starts, row pointers and the number of distinct blocks.  Row r
 // begins at the segment of its first sorted entry; rows without blocks take
 // the next row's start (every row_ptr entry has one writer).
-__global__ void __launch_bounds__(kAsmThreads) k_asm_rows(long long n_in, int n_rows, const uint64_t* __restrict__ key,
+__global__ void __launch_bounds__(kAsmThreads) k_asm_rows(long long n_in, int n_rows, int cb,
+                                                          const uint64_t* __restrict__ key,
                                                           const int* __restrict__ head, const int* __restrict__ seg,
                                                           int* __restrict__ seg_start, int* __restrict__ row_ptr,
                                                           int* __restrict__ flag) {
@@ -127,15 +131,15 @@ __global__ void __launch_bounds__(kAsmThreads) k_asm_rows(long long n_in, int n_
     }
     if (k >= n_in) return;
     const uint64_t kk = key[k];
-    const bool valid = kk < (1ull << kKeyBits) - 1;
-    const int r = static_cast<int>(kk >> 20);
+    const bool valid = kk < key_sentinel(cb);
+    const int r = static_cast<int>(kk >> cb);
     if (head[k] && valid) {
         seg_start[seg[k]] = static_cast<int>(k);
-        const int pr = k == 0 ? -1 : static_cast<int>(key[k - 1] >> 20);
+        const int pr = k == 0 ? -1 : static_cast<int>(key[k - 1] >> cb);
         for (int rr = pr + 1; rr <= r; ++rr) row_ptr[rr] = seg[k];
     }
     // the last valid entry closes the remaining rows and counts the blocks
-    const bool last = valid && (k + 1 == n_in || key[k + 1] >= (1ull << kKeyBits) - 1);
+    const bool last = valid && (k + 1 == n_in || key[k + 1] >= key_sentinel(cb));
     if (last) {
         const int total = seg[k] + head[k];
         for (int rr = r + 1; rr <= n_rows; ++rr) row_ptr[rr] = total;
@@ -152,7 +156,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_asm_rows(long long n_in, int n_
 // order (nine consecutive threads read one listed block).  The segment is
 // read kAsmBatch entries at a time: their positions, then their values, all
 // in flight together, then added in order.
-__global__ void __launch_bounds__(kAsmThreads) k_asm_reduce(int nnzb, const uint64_t* __restrict__ key,
+__global__ void __launch_bounds__(kAsmThreads) k_asm_reduce(int nnzb, int cb, const uint64_t* __restrict__ key,
                                                             const int* __restrict__ pos,
                                                             const int* __restrict__ seg_start,
                                                             const double* __restrict__ blocks,
@@ -174,23 +178,30 @@ __global__ void __launch_bounds__(kAsmThreads) k_asm_reduce(int nnzb, const uint
             if (e + j < e1) acc += x[j];
     }
     val[9LL * b + c] = acc;
-    if (c == 0) col_idx[b] = static_cast<int>(key[e0] & 0xFFFFFull);
+    if (c == 0) col_idx[b] = static_cast<int>(key[e0] & ((1ull << cb) - 1));
 }
 
-size_t tmp_bytes(long long n_in) {
+size_t tmp_bytes(long long n_in, int key_bits) {
     const int n = static_cast<int>(std::max<long long>(n_in, 1));
-    size_t sb = 0, cb = 0;
+    size_t sb = 0, scb = 0;
     rocprim::radix_sort_pairs(nullptr, sb, static_cast<uint64_t*>(nullptr), static_cast<uint64_t*>(nullptr),
-                              static_cast<int*>(nullptr), static_cast<int*>(nullptr), n, 0, kKeyBits);
-    rocprim::exclusive_scan(nullptr, cb, static_cast<int*>(nullptr), static_cast<int*>(nullptr), 0, n,
+                              static_cast<int*>(nullptr), static_cast<int*>(nullptr), n, 0, key_bits);
+    rocprim::exclusive_scan(nullptr, scb, static_cast<int*>(nullptr), static_cast<int*>(nullptr), 0, n,
                             rocprim::plus<int>());
-    return std::max(sb, cb);
+    return std::max(sb, scb);
+}
+
+// Bit width of the indices of an n_rows system: the smallest cb with
+// n_rows < 2^cb, so that every valid key stays below the sentinel.
+int index_bits(int n_rows) {
+    int cb = 1;
+    while (cb < 31 && (1LL << cb) <= n_rows) ++cb;
+    return cb;
 }
 
 }  // namespace
 
 AsmLayout assemble_layout(char* ws, int n_rows, long long n_in, size_t* total) {
-    (void)n_rows;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char* p = ws ? ws + off : nullptr;
@@ -207,7 +218,8 @@ AsmLayout assemble_layout(char* ws, int n_rows, long long n_in, size_t* total) {
     L.seg = reinterpret_cast<int*>(take(sizeof(int) * m));
     L.seg_start = reinterpret_cast<int*>(take(sizeof(int) * (m + 1)));
     L.flag = reinterpret_cast<int*>(take(sizeof(int) * 2));
-    L.tmp_bytes = tmp_bytes(n_in);
+    L.cb = index_bits(n_rows);
+    L.tmp_bytes = tmp_bytes(n_in, 2 * L.cb);
     L.tmp = take(L.tmp_bytes);
     if (total) *total = off;
     return L;
@@ -228,11 +240,12 @@ hipError_t launch_assemble_sort(const AsmLayout& L, int n_rows, long long n_in, 
     hipError_t e;
     if (n_in > 0) {
         const int g = ceil_div(n_in, kAsmThreads);
-        launch_kernel(k_asm_keys, dim3(g), dim3(kAsmThreads), 0, s, n_in, n_rows, rows, cols, L.key, L.pos, L.flag);
+        launch_kernel(k_asm_keys, dim3(g), dim3(kAsmThreads), 0, s, n_in, n_rows, L.cb, rows, cols, L.key, L.pos,
+                      L.flag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         size_t bytes = L.tmp_bytes;
         if ((e = rocprim::radix_sort_pairs(L.tmp, bytes, L.key, L.key_sorted, L.pos, L.pos_sorted,
-                                           static_cast<int>(n_in), 0, kKeyBits, s)) != hipSuccess)
+                                           static_cast<int>(n_in), 0, 2 * L.cb, s)) != hipSuccess)
             return e;
         launch_kernel(k_asm_heads, dim3(g), dim3(kAsmThreads), 0, s, n_in, static_cast<const uint64_t*>(L.key_sorted),
                       L.head);
@@ -241,12 +254,12 @@ hipError_t launch_assemble_sort(const AsmLayout& L, int n_rows, long long n_in, 
         if ((e = rocprim::exclusive_scan(L.tmp, bytes, L.head, L.seg, 0, static_cast<int>(n_in),
                                          rocprim::plus<int>(), s)) != hipSuccess)
             return e;
-        launch_kernel(k_asm_rows, dim3(g), dim3(kAsmThreads), 0, s, n_in, n_rows,
+        launch_kernel(k_asm_rows, dim3(g), dim3(kAsmThreads), 0, s, n_in, n_rows, L.cb,
                       static_cast<const uint64_t*>(L.key_sorted), static_cast<const int*>(L.head),
                       static_cast<const int*>(L.seg), L.seg_start, row_ptr, L.flag);
     } else {
         launch_kernel(k_asm_rows, dim3(ceil_div(n_rows + 1, kAsmThreads)), dim3(kAsmThreads), 0, s, 0LL, n_rows,
-                      static_cast<const uint64_t*>(L.key_sorted), static_cast<const int*>(L.head),
+                      L.cb, static_cast<const uint64_t*>(L.key_sorted), static_cast<const int*>(L.head),
                       static_cast<const int*>(L.seg), L.seg_start, row_ptr, L.flag);
     }
     return hipGetLastError();
@@ -256,7 +269,7 @@ hipError_t launch_assemble_reduce(const AsmLayout& L, long long n_in, const doub
                                   int nnzb, hipStream_t s) {
     (void)n_in;
     if (nnzb <= 0) return hipSuccess;
-    launch_kernel(k_asm_reduce, dim3(ceil_div(9LL * nnzb, kAsmThreads)), dim3(kAsmThreads), 0, s, nnzb,
+    launch_kernel(k_asm_reduce, dim3(ceil_div(9LL * nnzb, kAsmThreads)), dim3(kAsmThreads), 0, s, nnzb, L.cb,
                   static_cast<const uint64_t*>(L.key_sorted), static_cast<const int*>(L.pos_sorted),
                   static_cast<const int*>(L.seg_start), blocks, col_idx, val);
     return hipGetLastError();

@@ -187,7 +187,8 @@ hipError_t launch_apply_level0(const SolverView& v, bool f32, int mode, int k, h
 
 // assemble.hip: block-list assembly (scratch in the caller's workspace).
 struct AsmLayout {
-    uint64_t *key, *key_sorted;  // (row << 20) | col per listed block
+    int cb;                      // index bits: n_rows < 2^cb
+    uint64_t *key, *key_sorted;  // (row << cb) | col per listed block
     int *pos, *pos_sorted;       // list position of each listed block
     int *head, *seg;             // segment heads of the sorted list and their exclusive scan
     int *seg_start;              // first sorted entry of each distinct (row, col)

@@ -63,7 +63,8 @@ def test_assemble_head_segmented_reduce_example(dev):
         _same(got, oracle.assemble(n, seg[perm], np.zeros(seg.size, np.int64), blocks[perm]))
 
 
-@pytest.mark.parametrize("n,m,seed", [(7, 50, 0), (300, 20000, 1), (2000, 150000, 2)])
+@pytest.mark.parametrize("n,m,seed", [(1, 20, 3), (2, 40, 4), (7, 50, 0), (300, 20000, 1), (2000, 150000, 2),
+                                      (65536, 30000, 5), (3_000_000, 60000, 6)])
 def test_assemble_random_lists(dev, n, m, seed):
     _say("assemble random", n, m)
     rng = np.random.default_rng(seed)
