@@ -237,3 +237,53 @@ def test_hierarchy_device_argument_checks():
     assert call(ctypes.c_void_p(4096 + 8), need) == _lib.MAS_INVALID_ARG  # not 256-byte aligned
     assert call(ctypes.c_void_p(4096), need - 1) == _lib.MAS_WORKSPACE_TOO_SMALL
     assert S._L.mas_hierarchy_device(None, None, None, None, ctypes.c_void_p(4096), need, None) == _lib.MAS_INVALID_ARG
+
+
+def test_new_entry_points_argument_checks():
+    """mas_hierarchy_rebuild, abd_contact_blocks, bcsr_assemble and
+    mas_morton_partition reject bad arguments on the host, before any device
+    work."""
+    L = _lib.load()
+    vp = ctypes.c_void_p
+    s = small_cube()
+    S = MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16)
+    need = S._L.mas_hierarchy_workspace_size(S._h)
+    ws = vp(4096)
+    rb = lambda h, nnzb, rp, ci, u, sn, w, n: L.mas_hierarchy_rebuild(h, nnzb, rp, ci, u, sn, w, n, None)
+    assert rb(None, 10, ws, ws, ws, ws, ws, need) == _lib.MAS_INVALID_ARG
+    assert rb(S._h, -1, ws, ws, ws, ws, ws, need) == _lib.MAS_INVALID_ARG
+    assert rb(S._h, 10, None, ws, ws, ws, ws, need) == _lib.MAS_INVALID_ARG  # no row_ptr
+    assert rb(S._h, 10, ws, None, ws, ws, ws, need) == _lib.MAS_INVALID_ARG  # blocks but no col_idx
+    assert rb(S._h, 10, ws, ws, None, ws, ws, need) == _lib.MAS_INVALID_ARG  # no outputs
+    assert rb(S._h, 10, ws, ws, ws, ws, vp(4096 + 8), need) == _lib.MAS_INVALID_ARG  # misaligned workspace
+    assert rb(S._h, 10, ws, ws, ws, ws, ws, need - 1) == _lib.MAS_WORKSPACE_TOO_SMALL
+    h = ctypes.c_void_p()
+    assert L.mas_create(None, ctypes.byref(h)) == _lib.MAS_OK
+    assert rb(h, 10, ws, ws, ws, ws, ws, 1 << 20) == _lib.MAS_NOT_READY
+    L.mas_destroy(h)
+
+    n_out = ctypes.c_int64(0)
+    wsz = int(L.abd_contact_workspace_size(10, 4))
+    assert wsz > 0
+    ab = lambda n, m, levels, w, nb: L.abd_contact_blocks(n, ws, ws, ws, m, ws, ws, ws, levels, ws, ws, ws, 64,
+                                                         ctypes.byref(n_out), w, nb, None)
+    assert ab(0, 4, 2, ws, wsz) == _lib.MAS_INVALID_ARG  # no nodes
+    assert ab(10, -1, 2, ws, wsz) == _lib.MAS_INVALID_ARG
+    assert ab(10, 4, 3, ws, wsz) == _lib.MAS_INVALID_ARG  # levels must be 1 or 2
+    assert ab(10, 4, 2, vp(4096 + 8), wsz) == _lib.MAS_INVALID_ARG
+    assert ab(10, 4, 2, ws, wsz - 1) == _lib.MAS_WORKSPACE_TOO_SMALL
+
+    nb = ctypes.c_int64(0)
+    asm = lambda n_rows, n_in: L.bcsr_assemble(n_rows, n_in, ws, ws, ws, ws, ws, ws, 16, ctypes.byref(nb), ws,
+                                               1 << 30, None)
+    assert asm(0, 4) == _lib.MAS_INVALID_ARG
+    assert asm(0x7fffffff, 4) == _lib.MAS_INVALID_ARG  # n_rows + 1 must fit an int32 row_ptr
+    assert asm(10, -1) == _lib.MAS_INVALID_ARG
+    assert int(L.bcsr_assemble_workspace_size(3_000_000, 1000)) > 0  # beyond 2^20 rows
+
+    mw = int(L.mas_morton_workspace_size(100))
+    assert mw > 0
+    assert L.mas_morton_partition(0, ws, 16, ws, ws, mw, None) == _lib.MAS_INVALID_ARG
+    assert L.mas_morton_partition(100, ws, 0, ws, ws, mw, None) == _lib.MAS_INVALID_ARG
+    assert L.mas_morton_partition(100, ws, 16, ws, vp(4096 + 8), mw, None) == _lib.MAS_INVALID_ARG
+    assert L.mas_morton_partition(100, ws, 16, ws, ws, mw - 1, None) == _lib.MAS_WORKSPACE_TOO_SMALL
