@@ -339,6 +339,8 @@ size_t mas_hierarchy_workspace_size(const mas_handle* h);
  *       mas_get_ordering; any output may be NULL.
  *   workspace: device scratch, ws_bytes >= mas_hierarchy_workspace_size,
  *              256-byte aligned.
+ * After mas_replan the pattern is the replan's (its slot-ordered copy in
+ * the replan workspace).
  * Synchronises the stream.  Errors: MAS_NOT_READY, MAS_INVALID_ARG,
  * MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
 int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t* sn, void* workspace,
@@ -370,13 +372,48 @@ int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t
 int mas_hierarchy_rebuild(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
                           int32_t* out_units, int32_t* out_sn, void* workspace, size_t ws_bytes, void* stream);
 
+/* Device bytes of scratch mas_replan needs for a new pattern of nnzb
+ * blocks (0 before mas_analyze or for nnzb outside [1, 2^31 - 1]). */
+size_t mas_replan_workspace_size(const mas_handle* h, int64_t nnzb);
+
+/* Every solver plan of a new block pattern of H, derived on the device
+ * under the analysed level-0 partition: what Sec. 4.2 repeats each Newton
+ * iteration when contacts change H's pattern (Supp. Alg. 2-5 for the
+ * hierarchy, Supp. Eq. 5 for the coarse patterns and their reduction
+ * plans).  The pattern is checked and put in slot order by a stable sort;
+ * the hierarchy, the coarse patterns, the inversion gathers, the
+ * restriction and prolongation tables and the group-symmetric SpMV storage
+ * are built by sorts, scans and per-domain kernels, each equal bit for bit
+ * to what mas_analyze_partition computes on the host for the same pattern
+ * and partition.  The host reads back counts twice (the level count, then
+ * the array sizes) and orders the SpMV's work groups from their block
+ * counts; it analyses nothing.
+ *   nnzb, row_ptr, col_idx: device, the new pattern in the caller's node
+ *       order, with the rules of mas_analyze (n_rows of the analysis,
+ *       row_ptr[n_rows + 1] from 0 to nnzb, columns strictly ascending,
+ *       every diagonal block, a symmetric pattern); nnzb >= n_rows.
+ *   workspace: device scratch, ws_bytes >= mas_replan_workspace_size(h,
+ *       nnzb), 256-byte aligned.  It holds the new plans until mas_build
+ *       places them in the solver workspace, so it must stay allocated and
+ *       unchanged as long as the handle uses them (until the next
+ *       mas_analyze*, mas_replan or mas_destroy).
+ * On success the handle describes the new pattern: mas_get_info and
+ * mas_workspace_size give its sizes, and the next mas_build (on a matrix of
+ * the new pattern) places the plans and builds the preconditioner.  On an
+ * error the handle keeps its previous plans.  Synchronises the stream.
+ * Errors: MAS_NOT_READY, MAS_INVALID_ARG (also for a pattern that breaks
+ * the rules above), MAS_WORKSPACE_TOO_SMALL, MAS_HIP_ERROR. */
+int mas_replan(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx, void* workspace,
+               size_t ws_bytes, void* stream);
+
 /* Host copy of the handle's static description (after mas_analyze). */
 int mas_get_info(const mas_handle* h, mas_info* out);
 
 /* Host copies of the ordering: map[n_rows] (node -> level-0 slot),
  * remap[parts*domain_size] (slot -> node or -1), sn[levels*n_rows]
  * (unit of each node at each level; level 0 = slot).  Any pointer may be
- * NULL.  Errors: MAS_NOT_READY. */
+ * NULL.  After mas_replan, sn is read from the replan workspace (a
+ * synchronous device copy).  Errors: MAS_NOT_READY, MAS_HIP_ERROR. */
 int mas_get_ordering(const mas_handle* h, int32_t* map, int32_t* remap, int32_t* sn);
 
 /* Host copy of the domain inverses Inv_{l,d} = (S_d C_l H C_l^T S_d^T)^-1 of

@@ -44,6 +44,8 @@ SYMBOLS = (
     "mas_hierarchy_workspace_size",
     "mas_hierarchy_device",
     "mas_hierarchy_rebuild",
+    "mas_replan_workspace_size",
+    "mas_replan",
     "mas_get_info",
     "mas_get_ordering",
     "mas_get_inverses",
@@ -169,6 +171,10 @@ def load():
     L.mas_hierarchy_device.restype = ctypes.c_int
     L.mas_hierarchy_rebuild.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.mas_hierarchy_rebuild.restype = ctypes.c_int
+    L.mas_replan_workspace_size.argtypes = [vp, ctypes.c_int64]
+    L.mas_replan_workspace_size.restype = ctypes.c_size_t
+    L.mas_replan.argtypes = [vp, ctypes.c_int64, vp, vp, vp, ctypes.c_size_t, vp]
+    L.mas_replan.restype = ctypes.c_int
     L.pcg_solve.argtypes = [vp, P(MasBcsr), vp, vp, P(PcgOptions), P(PcgResult), vp]
     L.pcg_solve.restype = ctypes.c_int
     L.pcg_adjoint.argtypes = [vp, P(MasBcsr), vp, vp, vp, vp, i32, P(PcgOptions), P(PcgResult), vp]

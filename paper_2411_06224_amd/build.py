@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmaspcg.so")
 
-HIP_SOURCES = ["spmv.hip", "vectors.hip", "mas.hip", "assemble.hip", "hierarchy.hip", "morton.hip", "abd.hip", "abi.cpp"]
+HIP_SOURCES = ["spmv.hip", "vectors.hip", "mas.hip", "assemble.hip", "hierarchy.hip", "morton.hip", "abd.hip", "replan.hip", "abi.cpp"]
 HOST_SOURCES = ["planner.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -15,6 +15,7 @@
 #include "launch.hpp"
 #include "morton.hpp"
 #include "planner.hpp"
+#include "replan.hpp"
 #include "restrict.hpp"
 
 using namespace maspcg;
@@ -62,12 +63,43 @@ struct KernelTimer {
     int launches[kKSlots] = {0};
 };
 
+// Array sizes of a plan that the host does not hold when the plan was
+// derived on the device (mas_replan); a host analysis takes them from its
+// vectors.
+struct Shape {
+    size_t nsb = 0;               // stored blocks of the FP64 SpMV copy
+    size_t n_tidx = 0;            // transposed entries of the symmetric storage
+    size_t nnzA[kMaxLv] = {};     // blocks of A_l (level 0: nnzb)
+    size_t n_domblk[kMaxLv] = {}; // inversion gather entries of each level
+};
+
+Shape shape_of(const Plan& P) {
+    Shape S;
+    S.nsb = P.sym ? P.sci.size() : static_cast<size_t>(P.nnzb);
+    S.n_tidx = P.tidx.size();
+    for (int l = 0; l < P.L; ++l) {
+        S.nnzA[l] = l == 0 ? static_cast<size_t>(P.nnzb) : P.ciA[l].size();
+        S.n_domblk[l] = P.dom_blk[l].size();
+    }
+    return S;
+}
+
+// A plan derived on the device: its arrays stay in the replan workspace
+// until mas_build places them in the solver workspace.
+struct DevicePlan {
+    bool active = false;
+    ReplanLayout R{};
+    PlacedShape ps{};
+};
+
 }  // namespace
 
 struct mas_handle {
     mas_options opts{};
     bool analyzed = false;
     Plan plan;
+    Shape shape;
+    DevicePlan dev;
     Layout lay;
     std::vector<std::vector<int>> translated;  // level-1 reduction sources and level-0 domain blocks in caller order
     std::vector<int> gtab_i;                   // restriction tables of levels >= 2 as uploaded ([G][L-2][W1]):
@@ -152,7 +184,8 @@ void make_layout(mas_handle* h) {
     const int n = 3 * P.N;
     Y.remap = Y.take(I * P.NS);
     Y.map = Y.take(I * P.V);
-    const size_t nsb = P.sym ? P.sci.size() : static_cast<size_t>(P.nnzb);
+    const Shape& Z = h->shape;
+    const size_t nsb = Z.nsb;
     Y.perm_src = Y.take(I * nsb);
     // the FP32 copy of the mixed solve keeps the full storage (its SpMV is
     // faster there), with its own permutation when the FP64 copy is symmetric
@@ -161,38 +194,39 @@ void make_layout(mas_handle* h) {
     Y.ci0 = Y.take(I * P.nnzb);
     Y.lead1 = Y.take(I * P.NS);
     Y.lmask = Y.take(sizeof(uint64_t) * P.NS);
-    Y.anc = Y.take(I * P.anc.size());
-    Y.g_u1 = Y.take(I * P.g_u1.size());
-    Y.gu1_slot = Y.take(I * P.gu1_slot.size());
-    Y.gu1_mask = Y.take(sizeof(uint64_t) * P.gu1_mask.size());
-    Y.gw_pos = Y.take(I * P.gw_pos.size());
-    Y.gw_li = Y.take(I * P.gw_li.size());
-    Y.gw_mask = Y.take(sizeof(uint64_t) * P.gw_mask.size());
+    Y.anc = Y.take(I * static_cast<size_t>(std::max(P.L - 1, 0)) * P.NS);
+    Y.g_u1 = Y.take(I * (static_cast<size_t>(P.G) + 1));
+    const size_t gw1 = static_cast<size_t>(P.G) * P.W1, ggw = static_cast<size_t>(P.G) * P.GW;
+    Y.gu1_slot = Y.take(I * gw1);
+    Y.gu1_mask = Y.take(sizeof(uint64_t) * gw1);
+    Y.gw_pos = Y.take(I * ggw);
+    Y.gw_li = Y.take(I * ggw);
+    Y.gw_mask = Y.take(sizeof(uint64_t) * ggw);
     Y.gorder = Y.take(I * P.gorder.size());
     const size_t gtab = P.L > 2 ? static_cast<size_t>(P.G) * (P.L - 2) * P.W1 : 0;  // [G][L-2][W1]
     Y.ganc = Y.take(I * gtab);
     Y.gpos = Y.take(I * gtab);
     Y.gmask = Y.take(sizeof(uint64_t) * gtab);
     if (P.sym) {
-        Y.srp = Y.take(I * P.srp.size());
-        Y.sci = Y.take(I * P.sci.size());
-        Y.srow = Y.take(P.srow.size());
-        Y.tptr = Y.take(I * P.tptr.size());
-        Y.tidx = Y.take(I * P.tidx.size());
+        Y.srp = Y.take(I * (static_cast<size_t>(P.NS) + 1));
+        Y.sci = Y.take(I * nsb);
+        Y.srow = Y.take(nsb);
+        Y.tptr = Y.take(I * (static_cast<size_t>(P.NS) + 1));
+        Y.tidx = Y.take(I * Z.n_tidx);
     }
     for (int l = 0; l < P.L; ++l) {
         if (l >= 1) {
-            Y.red_ptr[l] = Y.take(I * P.red_ptr[l].size());
-            Y.red_src[l] = Y.take(I * P.red_src[l].size());
+            Y.red_ptr[l] = Y.take(I * (Z.nnzA[l] + 1));
+            Y.red_src[l] = Y.take(I * Z.nnzA[l - 1]);
         }
-        Y.dom_ptr[l] = Y.take(I * P.dom_ptr[l].size());
-        Y.dom_blk[l] = Y.take(I * P.dom_blk[l].size());
-        Y.dom_ab[l] = Y.take(I * P.dom_ab[l].size());
-        if (l >= 2) Y.cp_ptr[l] = Y.take(I * P.cp_ptr[l].size());
+        Y.dom_ptr[l] = Y.take(I * (static_cast<size_t>(P.ndom[l]) + 1));
+        Y.dom_blk[l] = Y.take(I * Z.n_domblk[l]);
+        Y.dom_ab[l] = Y.take(I * Z.n_domblk[l]);
+        if (l >= 2) Y.cp_ptr[l] = Y.take(I * (static_cast<size_t>(P.units[l]) + 1));
     }
     Y.H64 = Y.take(Dd * 9 * nsb);
     Y.H32 = mixed ? Y.take(F * 9 * static_cast<size_t>(P.nnzb)) : 0;
-    for (int l = 1; l < P.L; ++l) Y.A[l] = Y.take(Dd * 9 * P.ciA[l].size());
+    for (int l = 1; l < P.L; ++l) Y.A[l] = Y.take(Dd * 9 * Z.nnzA[l]);
     for (int l = 0; l < P.L; ++l) {
         const size_t cnt = static_cast<size_t>(P.ndom[l]) * n * n;
         const size_t cnt64 = (l == 0 && P.N == 16) ? static_cast<size_t>(P.ndom[l]) * kPacked : cnt;
@@ -239,7 +273,7 @@ SolverView view(const mas_handle* h) {
     v.RG = P.RG;
     v.G = P.G;
     v.sym = P.sym ? 1 : 0;
-    v.nsb = P.sym ? static_cast<int>(P.sci.size()) : P.nnzb;
+    v.nsb = static_cast<int>(h->shape.nsb);
     v.maxT = P.maxT;
     if (P.sym) {
         v.srp = at<int>(h, Y.srp);
@@ -313,7 +347,7 @@ BuildView build_view(const mas_handle* h) {
     for (int l = 0; l < P.L; ++l) {
         b.units[l] = P.units[l];
         b.ndom[l] = P.ndom[l];
-        b.nnzA[l] = l == 0 ? P.nnzb : static_cast<int>(P.ciA[l].size());
+        b.nnzA[l] = static_cast<int>(h->shape.nnzA[l]);
         if (l >= 1) {
             b.red_ptr[l] = at<int>(h, Y.red_ptr[l]);
             b.red_src[l] = at<int>(h, Y.red_src[l]);
@@ -393,6 +427,58 @@ int upload_plan(mas_handle* h, hipStream_t s) {
         HIP_TRY(hipMemcpyAsync(h->ws + Y.gpos, h->gtab_i.data() + gtab, sizeof(int) * gtab, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(h->ws + Y.gmask, h->gtab_m.data(), sizeof(uint64_t) * gtab, hipMemcpyHostToDevice, s));
     }
+    HIP_TRY(hipStreamSynchronize(s));  // the host vectors are pageable
+    return MAS_OK;
+}
+
+// A device-derived plan (mas_replan) into the solver workspace: the
+// partition's maps and the SpMV group order from the host, every other
+// array written on the device from the replan workspace.
+int place_device_plan(mas_handle* h, hipStream_t s) {
+    const Plan& P = h->plan;
+    const Layout& Y = h->lay;
+    auto put = [&](size_t off, const std::vector<int>& v) -> hipError_t {
+        if (v.empty()) return hipSuccess;
+        return hipMemcpyAsync(h->ws + off, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    };
+    HIP_TRY(put(Y.remap, P.remap));
+    HIP_TRY(put(Y.map, P.map));
+    if (!P.gorder.empty()) HIP_TRY(put(Y.gorder, P.gorder));
+    PlanDest D{};
+    D.perm_src = at<int>(h, Y.perm_src);
+    D.perm_full = at<int>(h, Y.perm_full);
+    D.rp0 = at<int>(h, Y.rp0);
+    D.ci0 = at<int>(h, Y.ci0);
+    D.lead1 = at<int>(h, Y.lead1);
+    D.lmask = at<uint64_t>(h, Y.lmask);
+    D.anc = at<int>(h, Y.anc);
+    D.g_u1 = at<int>(h, Y.g_u1);
+    D.gu1_slot = at<int>(h, Y.gu1_slot);
+    D.gu1_mask = at<uint64_t>(h, Y.gu1_mask);
+    D.gw_pos = at<int>(h, Y.gw_pos);
+    D.gw_li = at<int>(h, Y.gw_li);
+    D.gw_mask = at<uint64_t>(h, Y.gw_mask);
+    D.ganc = at<int>(h, Y.ganc);
+    D.gpos = at<int>(h, Y.gpos);
+    D.gmask = at<uint64_t>(h, Y.gmask);
+    if (P.sym) {
+        D.srp = at<int>(h, Y.srp);
+        D.sci = at<int>(h, Y.sci);
+        D.srow = at<uint8_t>(h, Y.srow);
+        D.tptr = at<int>(h, Y.tptr);
+        D.tidx = at<int>(h, Y.tidx);
+    }
+    for (int l = 0; l < P.L; ++l) {
+        if (l >= 1) {
+            D.red_ptr[l] = at<int>(h, Y.red_ptr[l]);
+            D.red_src[l] = at<int>(h, Y.red_src[l]);
+        }
+        D.dom_ptr[l] = at<int>(h, Y.dom_ptr[l]);
+        D.dom_blk[l] = at<int>(h, Y.dom_blk[l]);
+        D.dom_ab[l] = at<int>(h, Y.dom_ab[l]);
+        if (l >= 2) D.cp_ptr[l] = at<int>(h, Y.cp_ptr[l]);
+    }
+    HIP_TRY(replan_place(h->dev.R, h->dev.ps, D, s));
     HIP_TRY(hipStreamSynchronize(s));  // the host vectors are pageable
     return MAS_OK;
 }
@@ -590,6 +676,19 @@ void mas_destroy(mas_handle* h) {
 
 namespace {
 
+void set_fusion(mas_handle* h) {
+    const Plan& R = h->plan;
+    // three launches per iteration where the SpMV's restriction of q takes
+    // one pass of its threads (restrict_fast_ok): on systems whose groups
+    // have many more coarse units (a group of the membrane + bodies system
+    // has up to 448 writers), the longer restriction in the SpMV costs more
+    // than the x/r update launch it saves, and every iteration restricts r
+    // directly
+    h->fuse_ok = sizeof(double) * (3 * static_cast<size_t>(R.RG) + restrict_smem_doubles(R.RG, R.W1, R.L)) <=
+                     spmv_restrict_capacity() &&
+                 restrict_fast_ok(R.W1, R.GW, spmv_threads());
+}
+
 int analyze_impl(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row_ptr, const int32_t* col_idx,
                  const int32_t* g_ptr, const int32_t* g_adj, const int32_t* part, int32_t n_parts) {
     if (!h) return MAS_INVALID_ARG;
@@ -601,6 +700,7 @@ int analyze_impl(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row
     h->analyzed = true;
     h->built = false;
     h->uploaded_to = nullptr;
+    h->dev = DevicePlan{};
     // level-1 reduction sources and level-0 inversion blocks in caller block order
     h->translated.assign(2, {});
     const Plan& Q = h->plan;
@@ -610,17 +710,9 @@ int analyze_impl(mas_handle* h, int32_t n_rows, int32_t nnzb, const int32_t* row
     }
     h->translated[1].resize(Q.dom_blk[0].size());
     for (size_t k = 0; k < Q.dom_blk[0].size(); ++k) h->translated[1][k] = Q.perm_src[Q.dom_blk[0][k]];
+    h->shape = shape_of(h->plan);
     make_layout(h);
-    const Plan& R = h->plan;
-    // three launches per iteration where the SpMV's restriction of q takes
-    // one pass of its threads (restrict_fast_ok): on systems whose groups
-    // have many more coarse units (a group of the membrane + bodies system
-    // has up to 448 writers), the longer restriction in the SpMV costs more
-    // than the x/r update launch it saves, and every iteration restricts r
-    // directly
-    h->fuse_ok = sizeof(double) * (3 * static_cast<size_t>(R.RG) + restrict_smem_doubles(R.RG, R.W1, R.L)) <=
-                     spmv_restrict_capacity() &&
-                 restrict_fast_ok(R.W1, R.GW, spmv_threads());
+    set_fusion(h);
     return MAS_OK;
 }
 
@@ -659,7 +751,7 @@ int mas_build(mas_handle* h, const mas_bcsr* H, void* workspace, size_t ws_bytes
     h->ws_size = ws_bytes;
     h->built = false;
     if (h->uploaded_to != h->ws) {
-        int rc = upload_plan(h, s);
+        int rc = h->dev.active ? place_device_plan(h, s) : upload_plan(h, s);
         if (rc != MAS_OK) return rc;
         h->uploaded_to = h->ws;
     }
@@ -944,8 +1036,13 @@ int mas_hierarchy_device(mas_handle* h, int32_t* levels, int32_t* units, int32_t
     const Plan& P = h->plan;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const HierWs W = hier_ws(P, static_cast<char*>(workspace));
-    HIP_TRY(hipMemcpyAsync(W.rp, P.rp0.data(), sizeof(int) * (P.NS + 1), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(W.ci, P.ci0.data(), sizeof(int) * P.nnzb, hipMemcpyHostToDevice, s));
+    if (h->dev.active) {  // the slot-ordered pattern of the replan
+        HIP_TRY(hipMemcpyAsync(W.rp, h->dev.R.rp0, sizeof(int) * (P.NS + 1), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(W.ci, h->dev.R.ci0, sizeof(int) * P.nnzb, hipMemcpyDeviceToDevice, s));
+    } else {
+        HIP_TRY(hipMemcpyAsync(W.rp, P.rp0.data(), sizeof(int) * (P.NS + 1), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(W.ci, P.ci0.data(), sizeof(int) * P.nnzb, hipMemcpyHostToDevice, s));
+    }
     HIP_TRY(hipMemcpyAsync(W.remap, P.remap.data(), sizeof(int) * P.NS, hipMemcpyHostToDevice, s));
     const HierPattern pat{W.rp, W.ci, nullptr, P.nnzb};
     HIP_TRY(launch_hierarchy(W.H, P.NS, P.V, P.N, hier_level_cap(h), W.remap, pat, s));
@@ -995,6 +1092,114 @@ int mas_hierarchy_rebuild(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, c
     return MAS_OK;
 }
 
+size_t mas_replan_workspace_size(const mas_handle* h, int64_t nnzb) {
+    if (!h || !h->analyzed || nnzb < 1 || nnzb > 0x7fffffffLL) return 0;
+    const Plan& P = h->plan;
+    size_t t = 0;
+    replan_layout(nullptr, P.V, P.NS, P.G, nnzb, &t);
+    return t;
+}
+
+int mas_replan(mas_handle* h, int64_t nnzb, const int32_t* row_ptr, const int32_t* col_idx, void* workspace,
+               size_t ws_bytes, void* stream) {
+    if (!h) return MAS_INVALID_ARG;
+    if (!h->analyzed) return MAS_NOT_READY;
+    const Plan& P0 = h->plan;
+    if (nnzb < P0.V || nnzb > 0x7fffffffLL || !row_ptr || !col_idx) return MAS_INVALID_ARG;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % kAlign) return MAS_INVALID_ARG;
+    if (ws_bytes < mas_replan_workspace_size(h, nnzb)) return MAS_WORKSPACE_TOO_SMALL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const ReplanLayout R = replan_layout(static_cast<char*>(workspace), P0.V, P0.NS, P0.G, nnzb, nullptr);
+    HIP_TRY(hipMemcpyAsync(R.map, P0.map.data(), sizeof(int) * P0.V, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(R.remap, P0.remap.data(), sizeof(int) * P0.NS, hipMemcpyHostToDevice, s));
+    HIP_TRY(replan_validate_order_hierarchy(R, P0.V, P0.NS, P0.N, hier_level_cap(h), nnzb, row_ptr, col_idx, R.map,
+                                            R.remap, s));
+    ReplanCounts c{};
+    HierState st{};
+    HIP_TRY(hipMemcpyAsync(&c, R.counts, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&st, R.H.st, sizeof(st), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c.bad || c.nnz_distinct != nnzb) return MAS_INVALID_ARG;
+    ReplanShape S{};
+    S.V = P0.V;
+    S.N = P0.N;
+    S.NS = P0.NS;
+    S.M = P0.M;
+    S.L = st.levels;
+    S.G = P0.G;
+    S.RG = P0.RG;
+    S.nnzb = nnzb;
+    for (int l = 0; l < S.L; ++l) {
+        S.units[l] = st.units[l];
+        S.ndom[l] = (st.units[l] + S.N - 1) / S.N;
+    }
+    HIP_TRY(replan_sizes(R, S, s));
+    const int G = S.G;
+    std::vector<int> g_u1(static_cast<size_t>(G) + 1), gsz(3 * static_cast<size_t>(G));
+    HIP_TRY(hipMemcpyAsync(&c, R.counts, sizeof(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(g_u1.data(), R.g_u1, sizeof(int) * g_u1.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(gsz.data(), R.gstore, sizeof(int) * gsz.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+
+    // the new plan: the partition and its maps stay, every size is new
+    Plan Q;
+    Q.V = P0.V;
+    Q.N = P0.N;
+    Q.M = P0.M;
+    Q.No = P0.No;
+    Q.NS = P0.NS;
+    Q.L = S.L;
+    Q.nnzb = static_cast<int>(nnzb);
+    Q.part = P0.part;
+    Q.map = P0.map;
+    Q.remap = P0.remap;
+    Q.units.assign(S.units, S.units + S.L);
+    Q.ndom.assign(S.ndom, S.ndom + S.L);
+    Q.D0 = P0.D0;
+    Q.RG = P0.RG;
+    Q.G = P0.G;
+    Q.W1 = 1;
+    for (int g = 0; g < G; ++g) Q.W1 = std::max(Q.W1, g_u1[g + 1] - g_u1[g]);
+    Q.GW = S.L > 2 ? std::max(1, c.gw_max) : 1;
+    Q.n_cpart = S.L > 2 ? c.cbase[S.L] : 0;
+    long long n_sym = 0, n_tidx = 0;
+    Q.maxT = 0;
+    for (int g = 0; g < G; ++g) {
+        n_sym += gsz[G + g];
+        n_tidx += gsz[2 * static_cast<size_t>(G) + g];
+        Q.maxT = std::max(Q.maxT, gsz[2 * static_cast<size_t>(G) + g]);
+    }
+    Q.sym = Q.RG <= 256 && Q.maxT <= kMaxTransposed;
+    std::vector<long long> cnt(G);
+    for (int g = 0; g < G; ++g) cnt[g] = Q.sym ? gsz[G + g] : gsz[g];
+    Q.gorder = spmv_group_order(cnt);
+    Shape Z;
+    Z.nsb = Q.sym ? static_cast<size_t>(n_sym) : static_cast<size_t>(nnzb);
+    Z.n_tidx = static_cast<size_t>(n_tidx);
+    PlacedShape ps{};
+    ps.S = S;
+    ps.sym = Q.sym ? 1 : 0;
+    ps.W1 = Q.W1;
+    ps.GW = Q.GW;
+    for (int l = 0; l < S.L; ++l) {
+        const int nA = l == 0 ? static_cast<int>(nnzb) : c.nnzA[l];
+        Z.nnzA[l] = static_cast<size_t>(nA);
+        Z.n_domblk[l] = static_cast<size_t>(c.ndomblk[l]);
+        ps.nnzA[l] = nA;
+    }
+    h->plan = std::move(Q);
+    h->shape = Z;
+    h->translated.clear();
+    h->dev.active = true;
+    h->dev.R = R;
+    h->dev.ps = ps;
+    h->built = false;
+    h->uploaded_to = nullptr;
+    make_layout(h);
+    set_fusion(h);
+    return MAS_OK;
+}
+
 int mas_get_info(const mas_handle* h, mas_info* out) {
     if (!h || !out) return MAS_INVALID_ARG;
     if (!h->analyzed) return MAS_NOT_READY;
@@ -1009,11 +1214,11 @@ int mas_get_info(const mas_handle* h, mas_info* out) {
     for (int l = 0; l < P.L; ++l) {
         out->units[l] = P.units[l];
         out->domains[l] = P.ndom[l];
-        out->coarse_nnzb[l] = l == 0 ? P.nnzb : static_cast<int>(P.ciA[l].size());
+        out->coarse_nnzb[l] = static_cast<int>(h->shape.nnzA[l]);
     }
     out->workspace_bytes = static_cast<int64_t>(h->lay.total);
     out->inverse_bytes = static_cast<int64_t>(h->lay.inverse_bytes);
-    out->stored_blocks = P.sym ? static_cast<int32_t>(P.sci.size()) : P.nnzb;
+    out->stored_blocks = static_cast<int32_t>(h->shape.nsb);
     return MAS_OK;
 }
 
@@ -1023,7 +1228,14 @@ int mas_get_ordering(const mas_handle* h, int32_t* map, int32_t* remap, int32_t*
     const Plan& P = h->plan;
     if (map) std::memcpy(map, P.map.data(), sizeof(int) * P.map.size());
     if (remap) std::memcpy(remap, P.remap.data(), sizeof(int) * P.remap.size());
-    if (sn) std::memcpy(sn, P.sn.data(), sizeof(int) * P.sn.size());
+    if (sn && !h->dev.active) std::memcpy(sn, P.sn.data(), sizeof(int) * P.sn.size());
+    if (sn && h->dev.active) {  // from the hierarchy in the replan workspace (unchanged since mas_replan)
+        std::vector<int> slot_sn(static_cast<size_t>(P.L) * P.NS);
+        HIP_TRY(hipMemcpy(slot_sn.data(), h->dev.R.H.sn, sizeof(int) * slot_sn.size(), hipMemcpyDeviceToHost));
+        for (int l = 0; l < P.L; ++l)
+            for (int i = 0; i < P.V; ++i)
+                sn[static_cast<size_t>(l) * P.V + i] = slot_sn[static_cast<size_t>(l) * P.NS + P.map[i]];
+    }
     return MAS_OK;
 }
 

@@ -272,21 +272,28 @@ void symmetric_storage(Plan& P) {
 // groups (keeping neighbouring groups, which share halo entries, on one
 // XCD).  Otherwise gorder stays empty.
 void spmv_order(Plan& P) {
-    P.gorder.clear();
     const int G = P.G, NS = P.NS, RG = P.RG;
-    if (G <= 0) return;
     const std::vector<int>& rp = P.sym ? P.srp : P.rp0;
-    std::vector<long long> cnt(G);
-    double mean = 0.0;
+    std::vector<long long> cnt(std::max(G, 0));
     for (int g = 0; g < G; ++g) {
         const int r0 = g * RG, r1 = std::min(r0 + RG, NS);
         cnt[g] = rp[r1] - rp[r0];
-        mean += static_cast<double>(cnt[g]);
     }
+    P.gorder = spmv_group_order(cnt);
+}
+
+}  // namespace
+
+std::vector<int> spmv_group_order(const std::vector<long long>& cnt) {
+    const int G = static_cast<int>(cnt.size());
+    std::vector<int> gorder;
+    if (G <= 0) return gorder;
+    double mean = 0.0;
+    for (int g = 0; g < G; ++g) mean += static_cast<double>(cnt[g]);
     mean /= G;
     std::vector<int> heavy, light;
     for (int g = 0; g < G; ++g) (static_cast<double>(cnt[g]) > 1.5 * mean ? heavy : light).push_back(g);
-    if (heavy.empty()) return;
+    if (heavy.empty()) return gorder;
     std::stable_sort(heavy.begin(), heavy.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
     const int q = G / kXcdCount, rem = G % kXcdCount;
     std::array<std::vector<int>, kXcdCount> lists;
@@ -301,12 +308,11 @@ void spmv_order(Plan& P) {
     for (x = 0; x < kXcdCount; ++x)
         while (lists[x].size() < cap(x)) lists[x].push_back(light[li++]);
     // workgroup b = i kXcdCount + x runs the i-th group of XCD x's list
-    P.gorder.assign(G, -1);
+    gorder.assign(G, -1);
     for (x = 0; x < kXcdCount; ++x)
-        for (size_t i = 0; i < lists[x].size(); ++i) P.gorder[i * kXcdCount + x] = lists[x][i];
+        for (size_t i = 0; i < lists[x].size(); ++i) gorder[i * kXcdCount + x] = lists[x][i];
+    return gorder;
 }
-
-}  // namespace
 
 std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_idx, const int32_t* g_ptr,
                     const int32_t* g_adj, int N, int max_levels, Plan& P, const int32_t* part, int n_parts) {

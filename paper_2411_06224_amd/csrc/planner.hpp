@@ -112,6 +112,10 @@ struct Plan {
     std::vector<int> sn;  // [L * V] unit of each node per level (level 0 = slot), for reports
 };
 
+// Workgroup order of the SpMV from the stored blocks of each group (empty:
+// the contiguous per-XCD mapping).
+std::vector<int> spmv_group_order(const std::vector<long long>& cnt);
+
 // Returns "" on success or a message describing the invalid input.
 // part / n_parts (optional): a caller-given level-0 partition, used instead
 // of the recursive bisection of the node graph.

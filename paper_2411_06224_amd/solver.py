@@ -345,6 +345,28 @@ class MasPcg:
         self._hier_ws = ws  # kept until the next call: the queued kernels use it
         return units, sn
 
+    def replan(self, row_ptr, col_idx):
+        """Every solver plan of a new block pattern (device int32 row_ptr /
+        col_idx in node order, e.g. after contacts changed) derived on the
+        device under the analysed partition; the next :meth:`build` takes a
+        matrix of that pattern.  The scratch holding the plans is kept with
+        the handle."""
+        _need_cuda(row_ptr, "row_ptr", torch.int32)
+        _need_cuda(col_idx, "col_idx", torch.int32)
+        if row_ptr.numel() != self.n_rows + 1:
+            raise ValueError("row_ptr must have n_rows + 1 entries")
+        nnzb = col_idx.numel()
+        need = int(self._L.mas_replan_workspace_size(self._h, nnzb))
+        if need == 0:
+            raise MasError("mas_replan_workspace_size", MAS_INVALID_ARG)
+        ws = torch.empty(need + _ALIGN, dtype=torch.uint8, device=row_ptr.device)
+        base = (ws.data_ptr() + _ALIGN - 1) // _ALIGN * _ALIGN
+        check("mas_replan", self._L.mas_replan(self._h, nnzb, _ptr(row_ptr), _ptr(col_idx), ctypes.c_void_p(base),
+                                               ctypes.c_size_t(need), _stream()))
+        self._replan_ws = ws  # holds the plans until the handle is re-analysed or re-planned
+        self.nnzb = int(nnzb)
+        return self
+
     def timings(self):
         """Device ms of [coarse sums, inversion, H permute, PCG iterations] of the last calls."""
         out = (ctypes.c_double * 4)()

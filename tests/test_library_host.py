@@ -240,9 +240,9 @@ def test_hierarchy_device_argument_checks():
 
 
 def test_new_entry_points_argument_checks():
-    """mas_hierarchy_rebuild, abd_contact_blocks, bcsr_assemble and
-    mas_morton_partition reject bad arguments on the host, before any device
-    work."""
+    """mas_hierarchy_rebuild, mas_replan, abd_contact_blocks, bcsr_assemble
+    and mas_morton_partition reject bad arguments on the host, before any
+    device work."""
     L = _lib.load()
     vp = ctypes.c_void_p
     s = small_cube()
@@ -280,6 +280,24 @@ def test_new_entry_points_argument_checks():
     assert asm(0x7fffffff, 4) == _lib.MAS_INVALID_ARG  # n_rows + 1 must fit an int32 row_ptr
     assert asm(10, -1) == _lib.MAS_INVALID_ARG
     assert int(L.bcsr_assemble_workspace_size(3_000_000, 1000)) > 0  # beyond 2^20 rows
+
+    rw = int(L.mas_replan_workspace_size(S._h, s.col_idx.size))
+    assert rw > 0 and int(L.mas_replan_workspace_size(S._h, 0)) == 0
+    assert int(L.mas_replan_workspace_size(None, 10)) == 0
+    rpl = lambda h, nnzb, rp, ci, w, n: L.mas_replan(h, nnzb, rp, ci, w, n, None)
+    nz = int(s.col_idx.size)
+    assert rpl(None, nz, ws, ws, ws, rw) == _lib.MAS_INVALID_ARG
+    assert rpl(S._h, s.n - 1, ws, ws, ws, rw) == _lib.MAS_INVALID_ARG  # fewer blocks than diagonal blocks
+    assert rpl(S._h, 1 << 31, ws, ws, ws, rw) == _lib.MAS_INVALID_ARG
+    assert rpl(S._h, nz, None, ws, ws, rw) == _lib.MAS_INVALID_ARG
+    assert rpl(S._h, nz, ws, None, ws, rw) == _lib.MAS_INVALID_ARG
+    assert rpl(S._h, nz, ws, ws, vp(4096 + 8), rw) == _lib.MAS_INVALID_ARG  # misaligned workspace
+    assert rpl(S._h, nz, ws, ws, ws, rw - 1) == _lib.MAS_WORKSPACE_TOO_SMALL
+    h = ctypes.c_void_p()
+    assert L.mas_create(None, ctypes.byref(h)) == _lib.MAS_OK
+    assert rpl(h, nz, ws, ws, ws, rw) == _lib.MAS_NOT_READY
+    L.mas_destroy(h)
+    assert S.info()["nnzb"] == nz  # the refused calls left the handle as it was
 
     mw = int(L.mas_morton_workspace_size(100))
     assert mw > 0
