@@ -445,6 +445,55 @@ def main():
         }
         log(f"device hierarchy: {ms_hier:.3f} ms, units {got}")
 
+        # every solver plan re-derived on the device when contacts change the
+        # pattern (mas_replan): a handle analysed on the contact-free mesh
+        # pattern is re-planned for the pattern with the 20,000 contacts; the
+        # partition comes from the same mesh graph as the headline solver's,
+        # so the re-planned solve must repeat the headline solve bit for bit
+        n = s.n
+        deg = np.diff(s.gptr)
+        key = np.unique(np.concatenate([np.arange(n) * (n + 1),
+                                        np.repeat(np.arange(n), deg).astype(np.int64) * n + s.gadj]))
+        rp_free = np.concatenate([[0], np.cumsum(np.bincount(key // n, minlength=n))]).astype(np.int32)
+        ci_free = (key % n).astype(np.int32)
+        rsolver = mp.MasPcg(rp_free, ci_free, graph=(s.gptr, s.gadj), domain_size=args.domain_size)
+        rsolver.replan(H.row_ptr, H.col_idx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rsolver.replan(H.row_ptr, H.col_idx)
+        torch.cuda.synchronize()
+        ms_replan = 1e3 * (time.perf_counter() - t0) / args.steps
+        mp_map, _, _ = rsolver.ordering()
+        t0 = time.perf_counter()
+        hsolver = mp.MasPcg(s.row_ptr, s.col_idx, domain_size=args.domain_size,
+                            partition=mp_map // args.domain_size)
+        ms_host_replan = 1e3 * (time.perf_counter() - t0)
+        hsolver.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rsolver.build(H)  # places the plans, then the numeric build
+        torch.cuda.synchronize()
+        ms_place_build = 1e3 * (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        rsolver.build(H)
+        torch.cuda.synchronize()
+        ms_build = 1e3 * (time.perf_counter() - t0)
+        xr, rres = rsolver.solve(H, b, tol=args.tol)
+        x0, _ = step(solver, args.tol)
+        torch.cuda.synchronize()
+        out["replan_device"] = {
+            "ms": round(ms_replan, 4),
+            "host_analysis_same_partition_ms": round(ms_host_replan, 1),
+            "first_build_ms": round(ms_place_build, 3),
+            "build_ms": round(ms_build, 3),
+            "iterations": rres["iterations"],
+            "solve_equals_headline": bool(torch.equal(xr, x0)) and rres["iterations"] == res["iterations"],
+        }
+        log(f"device re-plan: {ms_replan:.3f} ms (host analysis {ms_host_replan:.1f} ms), "
+            f"{rres['iterations']} its, equal: {out['replan_device']['solve_equals_headline']}")
+        rsolver.close()
+
         # forward + adjoint (loss 0.5 ||x - x*||^2, FP32 dL/dH) vs forward
         xt = torch.as_tensor(np.random.default_rng(4).standard_normal(3 * s.n), device=dev)
         for _ in range(max(args.warmup, 1)):
