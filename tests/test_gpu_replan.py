@@ -286,6 +286,21 @@ def test_replan_rejects_bad_patterns(dev):
         assert r == r0 and torch.equal(x, x0), what
 
 
+@pytest.mark.parametrize("case", [(64, 60, 8), (512, 2000, 1003)])
+def test_replan_membrane(dev, case):
+    """The membrane with affine bodies (groups with hundreds of coarse
+    writers, 16 levels at full size), re-planned for its pattern plus
+    random couplings, in both precisions."""
+    _say("replan membrane", case)
+    s = synth.membrane_system(case[0], case[1], seed=case[2])
+    rp2, ci2, val2 = _add_pairs(s.row_ptr, s.col_idx, 500, seed=11)
+    for precision in ("f64", "mixed"):
+        A, B = _pair(s, rp2, ci2, 16, precision)
+        inf, res = _compare(A, B, rp2, ci2, val2, dev, tol=1e-6)
+        assert res["status"] == 0
+        print(precision, "levels", inf["levels"], "iterations", res["iterations"])
+
+
 @pytest.mark.slow
 def test_replan_large_cube(dev):
     """48^3 nodes with 20,000 contacts, re-planned from the contact-free
