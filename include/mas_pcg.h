@@ -385,9 +385,10 @@ size_t mas_replan_workspace_size(const mas_handle* h, int64_t nnzb);
  * restriction and prolongation tables and the group-symmetric SpMV storage
  * are built by sorts, scans and per-domain kernels, each equal bit for bit
  * to what mas_analyze_partition computes on the host for the same pattern
- * and partition.  The host reads back counts twice (the level count, then
- * the array sizes) and orders the SpMV's work groups from their block
- * counts; it analyses nothing.
+ * and partition.  The host reads back counts (the level count, each coarse
+ * level's block count to size the next level's sort, then the array sizes)
+ * and orders the SpMV's work groups from their block counts; it analyses
+ * nothing.
  *   nnzb, row_ptr, col_idx: device, the new pattern in the caller's node
  *       order, with the rules of mas_analyze (n_rows of the analysis,
  *       row_ptr[n_rows + 1] from 0 to nnzb, columns strictly ascending,

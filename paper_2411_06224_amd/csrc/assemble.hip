@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "launch.hpp"
+#include "replan.hpp"
 
 namespace maspcg {
 namespace {
@@ -237,12 +238,20 @@ hipError_t launch_scan(const int* in, int n, int* out, int* totals, hipStream_t 
 hipError_t launch_assemble_sort(const AsmLayout& L, int n_rows, long long n_in, const int* rows, const int* cols,
                                 int* row_ptr, hipStream_t s) {
     launch_kernel(k_fill_int, dim3(1), dim3(64), 0, s, L.flag, 2LL, 0);
+    if (n_in > 0)
+        launch_kernel(k_asm_keys, dim3(ceil_div(n_in, kAsmThreads)), dim3(kAsmThreads), 0, s, n_in, n_rows, L.cb, rows,
+                      cols, L.key, L.pos, L.flag);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_assemble_sort_keys(L, n_rows, n_in, row_ptr, s, false);
+}
+
+hipError_t launch_assemble_sort_keys(const AsmLayout& L, int n_rows, long long n_in, int* row_ptr, hipStream_t s,
+                                     bool clear_flag) {
+    if (clear_flag) launch_kernel(k_fill_int, dim3(1), dim3(64), 0, s, L.flag, 2LL, 0);
     hipError_t e;
     if (n_in > 0) {
         const int g = ceil_div(n_in, kAsmThreads);
-        launch_kernel(k_asm_keys, dim3(g), dim3(kAsmThreads), 0, s, n_in, n_rows, L.cb, rows, cols, L.key, L.pos,
-                      L.flag);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
         size_t bytes = L.tmp_bytes;
         if ((e = rocprim::radix_sort_pairs(L.tmp, bytes, L.key, L.key_sorted, L.pos, L.pos_sorted,
                                            static_cast<int>(n_in), 0, 2 * L.cb, s)) != hipSuccess)

@@ -145,16 +145,17 @@ __global__ void k_rp_up(int NS, const int* __restrict__ sn_l, const int* __restr
     if (u >= 0) up[u] = sn_next[s];
 }
 
-// Sort input of one coarsening: fine block p (row r: the last row starting
-// at or before p) -> (up[r], up[ci[p]]); positions past the fine pattern's
-// blocks get -1 (their keys sort last).
-__global__ void k_rp_coarse_keys(long long n, int rowsF, const int* __restrict__ rp, const int* __restrict__ ci,
-                                 const int* __restrict__ up, int* __restrict__ rows, int* __restrict__ cols) {
+// Sort keys of one coarsening: fine block p (row r: the last row starting
+// at or before p) -> (up[r] << cb) | up[ci[p]] with its position p;
+// positions past the fine pattern's blocks get the sentinel (sorted last).
+__global__ void k_rp_coarse_keys(long long n, int rowsF, int cb, const int* __restrict__ rp,
+                                 const int* __restrict__ ci, const int* __restrict__ up, uint64_t* __restrict__ key,
+                                 int* __restrict__ pos) {
     const long long p = static_cast<long long>(blockIdx.x) * kRpThreads + threadIdx.x;
     if (p >= n) return;
+    pos[p] = static_cast<int>(p);
     if (p >= rp[rowsF]) {
-        rows[p] = -1;
-        cols[p] = -1;
+        key[p] = sentinel(cb);
         return;
     }
     int lo = 0, hi = rowsF;  // largest r with rp[r] <= p
@@ -165,12 +166,25 @@ __global__ void k_rp_coarse_keys(long long n, int rowsF, const int* __restrict__
         else
             hi = m;
     }
-    rows[p] = up[lo];
-    cols[p] = up[ci[p]];
+    key[p] = (static_cast<uint64_t>(up[lo]) << cb) | static_cast<uint64_t>(up[ci[p]]);
+}
+
+// First position in [lo, hi) of the ascending a[] whose value is >= v.
+__device__ __forceinline__ int first_at_least(const int* __restrict__ a, int lo, int hi, int v) {
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (a[m] < v)
+            lo = m + 1;
+        else
+            hi = m;
+    }
+    return lo;
 }
 
 // Inversion gathers of one level: per row s the blocks (s, t) with
-// s <= t < (domain start) + N.  cnt[rows] = 0 closes the scan.
+// s <= t < (domain start) + N, a contiguous range of the row's ascending
+// columns (found by binary search: coarse rows can hold thousands of
+// blocks).  cnt[rows] = 0 closes the scan.
 __global__ void k_rp_dom_count(int rows, int N, const int* __restrict__ rp, const int* __restrict__ ci,
                                int* __restrict__ cnt) {
     const int s = blockIdx.x * kRpThreads + threadIdx.x;
@@ -179,13 +193,8 @@ __global__ void k_rp_dom_count(int rows, int N, const int* __restrict__ rp, cons
         cnt[s] = 0;
         return;
     }
-    const int hi = s / N * N + N;
-    int c = 0;
-    for (int p = rp[s]; p < rp[s + 1]; ++p) {
-        const int t = ci[p];
-        c += (t >= s && t < hi) ? 1 : 0;
-    }
-    cnt[s] = c;
+    const int p0 = first_at_least(ci, rp[s], rp[s + 1], s);
+    cnt[s] = first_at_least(ci, p0, rp[s + 1], s / N * N + N) - p0;
 }
 
 __global__ void k_rp_dom_fill(int rows, int N, const int* __restrict__ rp, const int* __restrict__ ci,
@@ -193,13 +202,13 @@ __global__ void k_rp_dom_fill(int rows, int N, const int* __restrict__ rp, const
                               int* __restrict__ ab) {
     const int s = blockIdx.x * kRpThreads + threadIdx.x;
     if (s >= rows) return;
-    const int lo = s / N * N, hi = lo + N;
+    const int lo = s / N * N;
+    const int p0 = first_at_least(ci, rp[s], rp[s + 1], s);
+    const int p1 = first_at_least(ci, p0, rp[s + 1], lo + N);
     int o = off[s];
-    for (int p = rp[s]; p < rp[s + 1]; ++p) {
-        const int t = ci[p];
-        if (t < s || t >= hi) continue;
+    for (int p = p0; p < p1; ++p) {
         blk[o] = perm ? perm[p] : p;
-        ab[o] = (s - lo) | ((t - lo) << 8);
+        ab[o] = (s - lo) | ((ci[p] - lo) << 8);
         ++o;
     }
 }
@@ -464,30 +473,36 @@ __global__ void k_rp_gtab(int G, int L, int W1, int NS, const int* __restrict__ 
 }
 
 // Writer tables [G][GW], levels then units in order: partial position,
-// entry (l - 2) W1 + i of the group's table row, member mask.
-__global__ void k_rp_gw(int G, int L, int W1, int GW, int NS, const int* __restrict__ g_u1,
-                        const int* __restrict__ anc1, const int* __restrict__ lpos, int* __restrict__ gw_pos,
-                        int* __restrict__ gw_li, uint64_t* __restrict__ gw_mask) {
-    const int g = blockIdx.x * kRpThreads + threadIdx.x;
-    if (g >= G) return;
+// entry (l - 2) W1 + i of the group's table row, member mask.  One wave per
+// group: the writers of 64 units at a time are ranked by a ballot.
+__global__ void __launch_bounds__(64) k_rp_gw(int L, int W1, int GW, int NS, const int* __restrict__ g_u1,
+                                              const int* __restrict__ anc1, const int* __restrict__ lpos,
+                                              int* __restrict__ gw_pos, int* __restrict__ gw_li,
+                                              uint64_t* __restrict__ gw_mask) {
+    const int g = blockIdx.x, lane = threadIdx.x;
     const int lo = g_u1[g], n1 = g_u1[g + 1] - lo;
     const size_t base = static_cast<size_t>(g) * GW;
     int e = 0;
     for (int l = 2; l < L; ++l) {
         const int* a = anc1 + static_cast<size_t>(l) * NS;
         const int* w = lpos + static_cast<size_t>(l) * NS;
-        for (int i = 0; i < n1; ++i) {
-            if (w[lo + i] < 0) continue;
-            gw_pos[base + e] = w[lo + i];
-            gw_li[base + e] = (l - 2) * W1 + i;
-            gw_mask[base + e] = W1 <= 64 ? writer_mask(a, lo, n1, i) : 0ull;
-            ++e;
+        for (int i0 = 0; i0 < n1; i0 += 64) {
+            const int i = i0 + lane;
+            const int ps = i < n1 ? w[lo + i] : -1;
+            const uint64_t writers = __ballot(ps >= 0);
+            if (ps >= 0) {
+                const size_t o = base + e + __popcll(writers & ((1ull << lane) - 1ull));
+                gw_pos[o] = ps;
+                gw_li[o] = (l - 2) * W1 + i;
+                gw_mask[o] = W1 <= 64 ? writer_mask(a, lo, n1, i) : 0ull;
+            }
+            e += __popcll(writers);
         }
     }
-    for (; e < GW; ++e) {
-        gw_pos[base + e] = -1;
-        gw_li[base + e] = 0;
-        gw_mask[base + e] = 0ull;
+    for (int k = e + lane; k < GW; k += 64) {
+        gw_pos[base + k] = -1;
+        gw_li[base + k] = 0;
+        gw_mask[base + k] = 0ull;
     }
 }
 
@@ -514,11 +529,11 @@ hipError_t coarsen_level(const ReplanLayout& R, int NS, int l, int rowsF, int ro
     launch_kernel(k_rp_up, dim3(grid(NS)), dim3(kRpThreads), 0, s, NS,
                   static_cast<const int*>(R.H.sn + static_cast<size_t>(l - 1) * NS),
                   static_cast<const int*>(R.H.sn + static_cast<size_t>(l) * NS), R.up);
-    launch_kernel(k_rp_coarse_keys, dim3(grid(nF)), dim3(kRpThreads), 0, s, nF, rowsF, rpF, ciF,
-                  static_cast<const int*>(R.up), R.rows, R.cols);
+    launch_kernel(k_rp_coarse_keys, dim3(grid(nF)), dim3(kRpThreads), 0, s, nF, rowsF, R.A.cb, rpF, ciF,
+                  static_cast<const int*>(R.up), R.A.key, R.A.pos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = launch_assemble_sort(R.A, rowsC, nF, R.rows, R.cols, rpC, s)) != hipSuccess) return e;
+    if ((e = launch_assemble_sort_keys(R.A, rowsC, nF, rpC, s, true)) != hipSuccess) return e;
     launch_kernel(k_rp_cols, dim3(grid(nF)), dim3(kRpThreads), 0, s, nF, R.A.cb,
                   static_cast<const uint64_t*>(R.A.key_sorted), static_cast<const int*>(R.A.seg_start),
                   static_cast<const int*>(R.A.flag + 1), ciC);
@@ -542,13 +557,6 @@ hipError_t dom_place(const ReplanLayout& R, int rows, int N, int nd, const int* 
     launch_kernel(k_rp_dom_ptr, dim3(grid(nd + 1)), dim3(kRpThreads), 0, s, rows, N, nd,
                   static_cast<const int*>(R.off), ptr);
     return hipGetLastError();
-}
-
-// Fine block bound of level l's pattern before its count is known.
-long long level_bound(const ReplanShape& S, int l) {
-    if (l == 0) return S.nnzb;
-    const long long u = S.units[l];
-    return std::min<long long>(S.nnzb, u * u);
 }
 
 }  // namespace
@@ -650,14 +658,23 @@ hipError_t replan_sizes(const ReplanLayout& R, const ReplanShape& S, hipStream_t
                   static_cast<const int*>(R.lead1), R.gcnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan(R, R.gcnt, R.g_u1, G + 1, s)) != hipSuccess) return e;
-    // coarse levels
+    // coarse levels; each level's block count is read back to size the next
+    // level's sort (sorting a bound instead costs a full-length sort per
+    // level: 4-5 ms over the 16 levels of the membrane with bodies)
+    long long nF = S.nnzb;
     for (int l = 1; l < L; ++l) {
         const int* rpF = l == 1 ? R.rp0 : R.rpX[(l - 1) & 1];
         const int* ciF = l == 1 ? R.ci0 : R.ciX[(l - 1) & 1];
-        if ((e = coarsen_level(R, NS, l, S.units[l - 1], S.units[l], level_bound(S, l - 1), rpF, ciF, R.rpX[l & 1],
-                               R.ciX[l & 1], s)) != hipSuccess)
+        if ((e = coarsen_level(R, NS, l, S.units[l - 1], S.units[l], nF, rpF, ciF, R.rpX[l & 1], R.ciX[l & 1], s)) !=
+            hipSuccess)
             return e;
         launch_kernel(k_rp_store, dim3(1), dim3(64), 0, s, &R.counts->nnzA[l], static_cast<const int*>(R.A.flag + 1));
+        if (l + 1 < L) {
+            int nC = 0;
+            if ((e = hipMemcpyAsync(&nC, R.A.flag + 1, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+            nF = nC;
+        }
         if ((e = dom_counts(R, S.units[l], S.N, R.rpX[l & 1], R.ciX[l & 1], s)) != hipSuccess) return e;
         launch_kernel(k_rp_store, dim3(1), dim3(64), 0, s, &R.counts->ndomblk[l],
                       static_cast<const int*>(R.off + S.units[l]));
@@ -724,7 +741,7 @@ hipError_t replan_place(const ReplanLayout& R, const PlacedShape& P, const PlanD
         launch_kernel(k_rp_gu1, dim3(grid(NS)), dim3(kRpThreads), 0, s, NS, RG, W1, static_cast<const int*>(R.lead1),
                       static_cast<const uint64_t*>(R.lmask), static_cast<const int*>(R.g_u1), D.gu1_slot,
                       D.gu1_mask);
-    launch_kernel(k_rp_gw, dim3(grid(G)), dim3(kRpThreads), 0, s, G, L, W1, P.GW, NS, static_cast<const int*>(R.g_u1),
+    launch_kernel(k_rp_gw, dim3(G), dim3(64), 0, s, L, W1, P.GW, NS, static_cast<const int*>(R.g_u1),
                   static_cast<const int*>(R.anc1), static_cast<const int*>(R.lpos), D.gw_pos, D.gw_li, D.gw_mask);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (L > 2) {

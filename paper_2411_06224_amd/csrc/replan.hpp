@@ -19,6 +19,12 @@
 
 namespace maspcg {
 
+// assemble.hip: launch_assemble_sort from keys and list positions already in
+// L.key / L.pos (keys of entries to leave out: (1 << 2 cb) - 1);
+// clear_flag: reset L.flag first.
+hipError_t launch_assemble_sort_keys(const AsmLayout& L, int n_rows, long long n_in, int* row_ptr, hipStream_t s,
+                                     bool clear_flag);
+
 // Counts read back between the passes (one struct in the replan workspace).
 struct ReplanCounts {
     int bad;                 // bit 0: row_ptr, 1: column range, 2: column order, 3: diagonal, 4: symmetry
@@ -65,8 +71,9 @@ struct ReplanShape {
     int units[kMaxLv], ndom[kMaxLv];
 };
 
-// Pass 1b, after the level count is known: counts of every level, the
-// level-1 restriction tables and the writers of levels >= 2.
+// Pass 1b, after the level count is known: counts of every level (each
+// coarse level's block count is read back to size the next level's sort),
+// the level-1 restriction tables and the writers of levels >= 2.
 hipError_t replan_sizes(const ReplanLayout& R, const ReplanShape& S, hipStream_t s);
 
 // Destinations in the solver workspace.

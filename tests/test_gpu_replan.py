@@ -301,6 +301,44 @@ def test_replan_membrane(dev, case):
         print(precision, "levels", inf["levels"], "iterations", res["iterations"])
 
 
+def test_newton_steps_on_device(dev):
+    """The per-Newton path with no host analysis, for two contact sets in
+    turn on a small membrane with bodies: contact Hessians reduced in two
+    levels and assembled with the system's own blocks on the GPU, the
+    solver re-planned from the assembled device pattern, built and solved.
+    Each step equals the host analysis of its pattern on the same partition
+    byte for byte, and ten iterations agree with the oracle (1e-10)."""
+    import paper_2411_06224_amd as mp
+    from synth.abd import body_contacts
+
+    _say("newton steps on device")
+    s = synth.membrane_system(16, 6, seed=5)
+    S = mp.MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16, poison=True)
+    part = S.ordering()[0] // 16
+    own_r = torch.as_tensor(np.repeat(np.arange(s.n, dtype=np.int32), np.diff(s.row_ptr)), device=dev)
+    own_c = torch.as_tensor(s.col_idx, device=dev)
+    own_v = torch.as_tensor(s.val.reshape(-1, 3, 3), device=dev)
+    for seed in (6, 8):
+        d = body_contacts(cells=16, n_bodies=6, n_vf=300, n_ee=60, seed=seed)
+        assert d["n_dof_rows"] == s.n
+        t = {k: torch.as_tensor(np.ascontiguousarray(d[k]), device=dev)
+             for k in ("node_row", "node_is_body", "node_xbar", "rows", "cols", "blocks")}
+        r2, c2, b2 = mp.abd_contact_blocks(d["n_nodes"], t["node_row"], t["node_is_body"], t["node_xbar"],
+                                           t["rows"], t["cols"], t["blocks"], levels=2)
+        Hg = mp.bcsr_assemble(s.n, torch.cat([own_r, r2]), torch.cat([own_c, c2]), torch.cat([own_v, b2]))
+        S.replan(Hg.row_ptr, Hg.col_idx)
+        rp, ci, val = Hg.row_ptr.cpu().numpy(), Hg.col_idx.cpu().numpy(), Hg.val.cpu().numpy()
+        assert ci.size > s.col_idx.size  # the contacts added blocks
+        B = mp.MasPcg(rp, ci, domain_size=16, partition=part, poison=True)
+        S._ws = None  # a fresh poisoned workspace for the byte comparison
+        _compare(S, B, rp, ci, val, dev, tol=1e-8, b=s.b)
+        P = oracle.MAS(rp, ci, val, N=16, part=part, M=int(part.max()) + 1)
+        xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
+        x, res = S.solve(Hg, torch.as_tensor(s.b, device=dev), tol=0.0, max_iter=10)
+        assert res["iterations"] == it == 10
+        assert np.linalg.norm(x.cpu().numpy() - xr) <= 1e-10 * np.linalg.norm(xr)
+
+
 @pytest.mark.slow
 def test_replan_large_cube(dev):
     """48^3 nodes with 20,000 contacts, re-planned from the contact-free
