@@ -232,6 +232,10 @@ def test_replan_back_and_forth(dev):
         B = MasPcg(rp, ci, domain_size=16, partition=part, poison=True)
         A._ws = None  # a fresh poisoned workspace, so that the byte comparison sees only this step's writes
         _compare(A, B, rp, ci, val, dev)
+        # the device hierarchy of a re-planned handle is built from the re-planned pattern
+        units, sn = A.hierarchy_device(dev)
+        inf = B.info()
+        assert list(units) == inf["units"] and np.array_equal(sn, B.ordering()[2])
 
 
 def test_replan_rejects_bad_patterns(dev):
