@@ -165,6 +165,34 @@ def test_replan_matches_host_plans(dev, name, N, precision):
     print("levels", inf["levels"], "units", inf["units"], "iterations", res["iterations"])
 
 
+TINY = {
+    "cube1": lambda: cube(1),
+    "cube2": lambda: cube(2),
+    "rand300_local": lambda: synth.random_spd_system(300, 700, seed=2, local=12),
+}
+
+
+@pytest.mark.parametrize("N", [1, 4, 16])
+@pytest.mark.parametrize("name", list(TINY))
+def test_replan_tiny_systems(dev, name, N):
+    """Small systems and domain sizes (a single domain, one node per
+    domain, padded slots), with contacts added and with the pattern
+    reduced to its diagonal (nothing merges: one level)."""
+    _say("replan tiny", name, N)
+    s = TINY[name]()
+    rp1, ci1 = _graph_pattern(s)
+    n = s.n
+    rp2, ci2, val2 = _add_pairs(rp1, ci1, max(2, n // 4), seed=N)
+    A, B = _pair(s, rp2, ci2, N)
+    _compare(A, B, rp2, ci2, val2, dev)
+    rpd = np.arange(n + 1, dtype=np.int32)
+    cid = np.arange(n, dtype=np.int32)
+    vald = np.tile(np.eye(3) * 4.0, (n, 1, 1))
+    A, B = _pair(s, rpd, cid, N)
+    inf, _ = _compare(A, B, rpd, cid, vald, dev)
+    assert inf["levels"] == 1
+
+
 def test_replan_deep_hierarchy(dev):
     """A pattern whose hierarchy reaches the 16-level limit."""
     _say("replan deep")
