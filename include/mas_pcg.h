@@ -135,7 +135,9 @@ void mas_destroy(mas_handle* h);
  * M = ceil(V/(N - N_o)) parts of at most N nodes with the smallest slack N_o
  * (Eq. num_subdomains), map/remap with -1 padding, supernode hierarchy from
  * the block pattern of H (contact couplings included), and every gather /
- * reduction plan the device phases use.
+ * reduction plan the device phases use.  When contacts later change the
+ * pattern, mas_replan derives the plans again on the device under this
+ * partition.
  *   row_ptr, col_idx: host copies of H's pattern (conventions above).
  *   g_ptr, g_adj: host CSR node graph to partition (e.g. mesh edges); both
  *                 NULL = the off-diagonal pattern of H.  Self loops and
