@@ -669,15 +669,15 @@ hipError_t replan_sizes(const ReplanLayout& R, const ReplanShape& S, hipStream_t
             hipSuccess)
             return e;
         launch_kernel(k_rp_store, dim3(1), dim3(64), 0, s, &R.counts->nnzA[l], static_cast<const int*>(R.A.flag + 1));
-        if (l + 1 < L) {
+        if ((e = dom_counts(R, S.units[l], S.N, R.rpX[l & 1], R.ciX[l & 1], s)) != hipSuccess) return e;
+        launch_kernel(k_rp_store, dim3(1), dim3(64), 0, s, &R.counts->ndomblk[l],
+                      static_cast<const int*>(R.off + S.units[l]));
+        if (l + 1 < L) {  // queued behind the gather counts, which run meanwhile
             int nC = 0;
             if ((e = hipMemcpyAsync(&nC, R.A.flag + 1, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
             if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
             nF = nC;
         }
-        if ((e = dom_counts(R, S.units[l], S.N, R.rpX[l & 1], R.ciX[l & 1], s)) != hipSuccess) return e;
-        launch_kernel(k_rp_store, dim3(1), dim3(64), 0, s, &R.counts->ndomblk[l],
-                      static_cast<const int*>(R.off + S.units[l]));
     }
     // writers of levels >= 2
     if (L > 2) {

@@ -38,7 +38,7 @@ struct ReplanCounts {
 struct ReplanLayout {
     HierLayout H;            // hierarchy: sn[l NS + slot], level state
     AsmLayout A;             // sort scratch over nnzb entries, keys over NS indices
-    int *rows, *cols;        // sort input [nnzb]
+    int *rows, *cols;        // slot-order sort input [nnzb]
     int *rp0, *ci0, *perm;   // slot-ordered pattern [NS + 1], [nnzb], [nnzb] (perm: caller block of each)
     int *rpX[2], *ciX[2];    // coarse patterns of consecutive levels [NS + 1], [nnzb]
     int* up;                 // level-l unit -> level-(l+1) unit [NS]
