@@ -148,6 +148,9 @@ CASES = {
     "cube8_800": lambda: (small_cube(), 800),
     "contact6_300": lambda: (cube(6, E=1e6, nu=0.49, seed=21, n_contacts=60), 300),
     "local2000_500": lambda: (synth.random_spd_system(2000, 6000, seed=6, local=30), 500),
+    # dense local rows: groups with more transposed entries than the
+    # symmetric storage holds, so the SpMV keeps the full storage
+    "dense_local_100": lambda: (synth.random_spd_system(2000, 90000, seed=6, local=60), 100),
 }
 
 
@@ -162,6 +165,8 @@ def test_replan_matches_host_plans(dev, name, N, precision):
     A, B = _pair(s, rp2, ci2, N, precision)
     inf, res = _compare(A, B, rp2, ci2, val2, dev, tol=1e-8)
     assert res["status"] == 0
+    if name == "dense_local_100" and N == 16:
+        assert inf["stored_blocks"] == inf["nnzb"]  # the full-storage case is covered
     print("levels", inf["levels"], "units", inf["units"], "iterations", res["iterations"])
 
 
@@ -372,16 +377,17 @@ def test_newton_steps_on_device(dev):
 
 
 @pytest.mark.slow
-def test_replan_large_cube(dev):
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_replan_large_cube(dev, precision):
     """48^3 nodes with 20,000 contacts, re-planned from the contact-free
     pattern; the time of the device re-plan is printed beside the host
     analysis of the same pattern and partition."""
     from paper_2411_06224_amd import MasPcg
 
-    _say("replan 48^3")
+    _say("replan 48^3", precision)
     s = large_cube()
     rp1, ci1 = _graph_pattern(s)
-    A = MasPcg(rp1, ci1, graph=(s.gptr, s.gadj), domain_size=16, poison=True)
+    A = MasPcg(rp1, ci1, graph=(s.gptr, s.gadj), domain_size=16, precision=precision, poison=True)
     rp_d = torch.as_tensor(s.row_ptr, device=dev)
     ci_d = torch.as_tensor(s.col_idx, device=dev)
     A.replan(rp_d, ci_d)  # warm-up (code objects, allocator)
@@ -394,7 +400,7 @@ def test_replan_large_cube(dev):
         times.append(time.perf_counter() - t0)
     mp_, _, _ = A.ordering()
     t0 = time.perf_counter()
-    B = MasPcg(s.row_ptr, s.col_idx, domain_size=16, partition=mp_ // 16, poison=True)
+    B = MasPcg(s.row_ptr, s.col_idx, domain_size=16, partition=mp_ // 16, precision=precision, poison=True)
     t_host = time.perf_counter() - t0
     inf, res = _compare(A, B, s.row_ptr, s.col_idx, s.val, dev, tol=1e-4, b=s.b)
     print(f"replan on the device {1e3 * min(times):.2f} ms; host analysis {1e3 * t_host:.1f} ms; "
