@@ -247,6 +247,33 @@ def test_replan_contact_system_against_oracle(dev):
     assert np.linalg.norm(x - xr) <= 1e-10 * np.linalg.norm(xr)
 
 
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_replan_adjoint(dev, precision):
+    """The adjoint solve and the dL/dH scatter of a re-planned handle equal
+    those of the host-planned handle, bit for bit."""
+    from paper_2411_06224_amd import BlockMatrix
+
+    _say("replan adjoint", precision)
+    s, n_pairs = CASES["contact6_300"]()
+    rp1, ci1 = _graph_pattern(s)
+    rp2, ci2, val2 = _add_pairs(rp1, ci1, n_pairs, seed=2)
+    A, B = _pair(s, rp2, ci2, 16, precision)
+    H = BlockMatrix.from_numpy(rp2, ci2, val2, device=dev)
+    rng = np.random.default_rng(4)
+    b = torch.as_tensor(rng.standard_normal(3 * s.n), device=dev)
+    g = torch.as_tensor(rng.standard_normal(3 * s.n), device=dev)
+    out = []
+    for S in (A, B):
+        S.build(H)
+        x, _ = S.solve(H, b, tol=1e-10)
+        lam, dH, res = S.adjoint(H, x, g, tol=1e-10)
+        out.append((x, lam, dH, res))
+    torch.cuda.synchronize()
+    (xa, la, da, ra), (xb, lb, db, rb) = out
+    assert ra == rb and ra["status"] == 0
+    assert torch.equal(xa, xb) and torch.equal(la, lb) and torch.equal(da, db)
+
+
 def test_replan_back_and_forth(dev):
     """Contacts appear, change and disappear: three re-plans in a row on one
     handle, each checked against the host analysis of its pattern."""
