@@ -33,26 +33,36 @@ struct Graph {
     std::vector<int> off, nbr;
 };
 
+// Both directions of every edge (self loops and out-of-range ends
+// dropped), each node's neighbours ascending and distinct: the edge list
+// bucketed by node, then each bucket sorted.
 Graph symmetrize(int V, const int32_t* ptr, const int32_t* adj) {
-    std::vector<std::pair<int, int>> e;
-    e.reserve(ptr ? 2 * static_cast<size_t>(ptr[V]) : 0);
+    std::vector<int> start(V + 1, 0);
     for (int i = 0; i < V; ++i)
         for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
-            int j = adj[p];
+            const int j = adj[p];
             if (j < 0 || j >= V || j == i) continue;
-            e.emplace_back(i, j);
-            e.emplace_back(j, i);
+            start[i + 1]++;
+            start[j + 1]++;
         }
-    std::sort(e.begin(), e.end());
-    e.erase(std::unique(e.begin(), e.end()), e.end());
+    for (int i = 0; i < V; ++i) start[i + 1] += start[i];
+    std::vector<int> fill(start.begin(), start.end() - 1), nb(start[V]);
+    for (int i = 0; i < V; ++i)
+        for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+            const int j = adj[p];
+            if (j < 0 || j >= V || j == i) continue;
+            nb[fill[i]++] = j;
+            nb[fill[j]++] = i;
+        }
     Graph g;
     g.off.assign(V + 1, 0);
-    g.nbr.resize(e.size());
-    for (size_t k = 0; k < e.size(); ++k) {
-        g.off[e[k].first + 1]++;
-        g.nbr[k] = e[k].second;
+    g.nbr.reserve(nb.size());
+    for (int i = 0; i < V; ++i) {
+        std::sort(nb.begin() + start[i], nb.begin() + start[i + 1]);
+        for (int q = start[i]; q < start[i + 1]; ++q)
+            if (q == start[i] || nb[q] != nb[q - 1]) g.nbr.push_back(nb[q]);
+        g.off[i + 1] = static_cast<int>(g.nbr.size());
     }
-    for (int i = 0; i < V; ++i) g.off[i + 1] += g.off[i];
     return g;
 }
 
@@ -61,10 +71,14 @@ class Bisection {
     explicit Bisection(const Graph& g) : g_(g), in_(g.off.size() - 1, -1), seen_(g.off.size() - 1, -1), depth_(g.off.size() - 1, 0) {}
 
     // Fills part[] by recursive bisection of all nodes into k parts.
+    // nodes[lo, hi) holds a set in its BFS order, asc_[lo, hi) the same set
+    // ascending (split from the parent's ascending list, not sorted again).
     void run(int k, std::vector<int>& part) {
         const int V = static_cast<int>(in_.size());
         std::vector<int> nodes(V);
         std::iota(nodes.begin(), nodes.end(), 0);
+        asc_.assign(nodes.begin(), nodes.end());
+        tmp_.resize(V);
         struct Task {
             int lo, hi, k;
         };
@@ -81,7 +95,10 @@ class Bisection {
             const int kl = t.k / 2;
             const int n = t.hi - t.lo;
             const int nl = static_cast<int>(static_cast<long long>(n) * kl / t.k);
-            if (n > 0) reorder(nodes.data() + t.lo, n);
+            if (n > 0) {
+                reorder(nodes.data() + t.lo, asc_.data() + t.lo, n);
+                split_ascending(nodes.data() + t.lo, asc_.data() + t.lo, n, nl);
+            }
             // left half is emitted first: push it last
             stack.push_back({t.lo + nl, t.hi, t.k - kl});
             stack.push_back({t.lo, t.lo + nl, kl});
@@ -111,12 +128,11 @@ class Bisection {
         return deepest;
     }
 
-    void reorder(int* S, int n) {
+    // asc: the set ascending.
+    void reorder(int* S, const int* asc, int n) {
         set_ = ++tag_;
         for (int q = 0; q < n; ++q) in_[S[q]] = set_;
-        std::vector<int> asc(S, S + n);
-        std::sort(asc.begin(), asc.end());
-        int root = asc.front();
+        int root = asc[0];
         std::vector<int> visit;
         visit.reserve(n);
         for (int rep = 0; rep < 2; ++rep) {
@@ -139,8 +155,21 @@ class Bisection {
         std::copy(visit.begin(), visit.end(), S);
     }
 
+    // asc (the set ascending) reordered into the ascending lists of the
+    // first nl nodes of S and of the rest.
+    void split_ascending(const int* S, int* asc, int n, int nl) {
+        const int left = ++tag_;
+        for (int q = 0; q < nl; ++q) in_[S[q]] = left;
+        int a = 0, b = nl;
+        for (int q = 0; q < n; ++q) {
+            const int v = asc[q];
+            tmp_[in_[v] == left ? a++ : b++] = v;
+        }
+        std::copy(tmp_.begin(), tmp_.begin() + n, asc);
+    }
+
     const Graph& g_;
-    std::vector<int> in_, seen_, depth_;
+    std::vector<int> in_, seen_, depth_, asc_, tmp_;
     int tag_ = 0, set_ = -1, mark_ = -1;
 };
 
@@ -175,18 +204,29 @@ int components(int units, int N, const std::vector<int>& rp, const std::vector<i
 }
 
 // Galerkin pattern and reduction plan: block (s, t) of the fine matrix goes
-// to block (up[s], up[t]) of the coarse one.
+// to block (up[s], up[t]) of the coarse one.  The fine blocks are ordered
+// by (up[s], up[t]), equal pairs in block order: a stable counting sort by
+// up[t], then one by up[s].
 void coarsen(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<int>& up, int coarse_units,
              std::vector<int>& rpC, std::vector<int>& ciC, std::vector<int>& red_ptr, std::vector<int>& red_src) {
     const int fine_units = static_cast<int>(rp.size()) - 1;
     const int nnz = rp.back();
     std::vector<long long> key(nnz);
+    std::vector<int> row(nnz);
     for (int s = 0; s < fine_units; ++s)
-        for (int p = rp[s]; p < rp[s + 1]; ++p)
+        for (int p = rp[s]; p < rp[s + 1]; ++p) {
             key[p] = static_cast<long long>(up[s]) * coarse_units + up[ci[p]];
+            row[p] = up[s];
+        }
+    std::vector<int> by_col(nnz), cnt(coarse_units + 1);
+    for (int p = 0; p < nnz; ++p) cnt[up[ci[p]] + 1]++;
+    for (int c = 0; c < coarse_units; ++c) cnt[c + 1] += cnt[c];
+    for (int p = 0; p < nnz; ++p) by_col[cnt[up[ci[p]]]++] = p;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int p = 0; p < nnz; ++p) cnt[row[p] + 1]++;
+    for (int c = 0; c < coarse_units; ++c) cnt[c + 1] += cnt[c];
     red_src.resize(nnz);
-    std::iota(red_src.begin(), red_src.end(), 0);
-    std::stable_sort(red_src.begin(), red_src.end(), [&](int a, int b) { return key[a] < key[b]; });
+    for (int q = 0; q < nnz; ++q) red_src[cnt[row[by_col[q]]]++] = by_col[q];
     rpC.assign(coarse_units + 1, 0);
     ciC.clear();
     red_ptr.assign(1, 0);
