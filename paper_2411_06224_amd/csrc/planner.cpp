@@ -268,6 +268,9 @@ void symmetric_storage(Plan& P) {
     P.sci.clear();
     P.sperm.clear();
     P.srow.clear();
+    P.sci.reserve(P.ci0.size());
+    P.sperm.reserve(P.ci0.size());
+    P.srow.reserve(P.ci0.size());
     std::vector<int> cnt(NS + 1, 0);
     for (int s = 0; s < NS; ++s) {
         const int r0 = s / RG * RG, r1 = std::min(r0 + RG, NS);
