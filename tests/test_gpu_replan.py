@@ -365,7 +365,8 @@ def test_replan_membrane(dev, case):
         print(precision, "levels", inf["levels"], "iterations", res["iterations"])
 
 
-def test_newton_steps_on_device(dev):
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_newton_steps_on_device(dev, precision):
     """The per-Newton path with no host analysis, for two contact sets in
     turn on a small membrane with bodies: contact Hessians reduced in two
     levels and assembled with the system's own blocks on the GPU, the
@@ -375,9 +376,9 @@ def test_newton_steps_on_device(dev):
     import paper_2411_06224_amd as mp
     from synth.abd import body_contacts
 
-    _say("newton steps on device")
+    _say("newton steps on device", precision)
     s = synth.membrane_system(16, 6, seed=5)
-    S = mp.MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16, poison=True)
+    S = mp.MasPcg(s.row_ptr, s.col_idx, graph=(s.gptr, s.gadj), domain_size=16, precision=precision, poison=True)
     part = S.ordering()[0] // 16
     own_r = torch.as_tensor(np.repeat(np.arange(s.n, dtype=np.int32), np.diff(s.row_ptr)), device=dev)
     own_c = torch.as_tensor(s.col_idx, device=dev)
@@ -393,9 +394,11 @@ def test_newton_steps_on_device(dev):
         S.replan(Hg.row_ptr, Hg.col_idx)
         rp, ci, val = Hg.row_ptr.cpu().numpy(), Hg.col_idx.cpu().numpy(), Hg.val.cpu().numpy()
         assert ci.size > s.col_idx.size  # the contacts added blocks
-        B = mp.MasPcg(rp, ci, domain_size=16, partition=part, poison=True)
+        B = mp.MasPcg(rp, ci, domain_size=16, partition=part, precision=precision, poison=True)
         S._ws = None  # a fresh poisoned workspace for the byte comparison
         _compare(S, B, rp, ci, val, dev, tol=1e-8, b=s.b)
+        if precision != "f64":
+            continue  # the oracle comparison below is the FP64 one
         P = oracle.MAS(rp, ci, val, N=16, part=part, M=int(part.max()) + 1)
         xr, st, it, *_ = P.pcg(s.b, tol=0.0, max_iter=10)
         x, res = S.solve(Hg, torch.as_tensor(s.b, device=dev), tol=0.0, max_iter=10)
