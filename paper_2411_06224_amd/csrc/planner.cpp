@@ -25,6 +25,7 @@
 #include <array>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace maspcg {
 namespace {
@@ -66,42 +67,51 @@ Graph symmetrize(int V, const int32_t* ptr, const int32_t* adj) {
     return g;
 }
 
+// A set of the recursion: nodes[lo, hi) (in the parent's BFS order), to be
+// cut into k parts numbered from p0.
+struct BisectTask {
+    int lo, hi, k, p0;
+};
+
+// One worker of the recursive bisection.  nodes[] and asc[] are shared by
+// all workers, each task owning its range: asc[lo, hi) holds the task's set
+// ascending (split from the parent's ascending list, not sorted again).
+// Each worker has its own membership tags, so workers on disjoint tasks do
+// not interact, and a task's split depends on its set alone: the parts do
+// not depend on how the tasks are spread over workers.
 class Bisection {
   public:
-    explicit Bisection(const Graph& g) : g_(g), in_(g.off.size() - 1, -1), seen_(g.off.size() - 1, -1), depth_(g.off.size() - 1, 0) {}
+    Bisection(const Graph& g, int* nodes, int* asc)
+        : g_(g), nodes_(nodes), asc_(asc), in_(g.off.size() - 1, -1), seen_(g.off.size() - 1, -1),
+          depth_(g.off.size() - 1, 0), tmp_(g.off.size() - 1) {}
 
-    // Fills part[] by recursive bisection of all nodes into k parts.
-    // nodes[lo, hi) holds a set in its BFS order, asc_[lo, hi) the same set
-    // ascending (split from the parent's ascending list, not sorted again).
-    void run(int k, std::vector<int>& part) {
-        const int V = static_cast<int>(in_.size());
-        std::vector<int> nodes(V);
-        std::iota(nodes.begin(), nodes.end(), 0);
-        asc_.assign(nodes.begin(), nodes.end());
-        tmp_.resize(V);
-        struct Task {
-            int lo, hi, k;
-        };
-        std::vector<Task> stack{{0, V, k}};
-        int next_part = 0;
+    // Splits t (k >= 2) into its left and right tasks.
+    void split(const BisectTask& t, BisectTask& left, BisectTask& right) {
+        const int kl = t.k / 2;
+        const int n = t.hi - t.lo;
+        const int nl = static_cast<int>(static_cast<long long>(n) * kl / t.k);
+        if (n > 0) {
+            reorder(nodes_ + t.lo, asc_ + t.lo, n);
+            split_ascending(nodes_ + t.lo, asc_ + t.lo, n, nl);
+        }
+        left = {t.lo, t.lo + nl, kl, t.p0};
+        right = {t.lo + nl, t.hi, t.k - kl, t.p0 + kl};
+    }
+
+    // The whole subtree of t: part[node] for its nodes.
+    void finish(const BisectTask& root, int* part) {
+        std::vector<BisectTask> stack{root};
         while (!stack.empty()) {
-            Task t = stack.back();
+            const BisectTask t = stack.back();
             stack.pop_back();
             if (t.k == 1) {
-                for (int q = t.lo; q < t.hi; ++q) part[nodes[q]] = next_part;
-                ++next_part;
+                for (int q = t.lo; q < t.hi; ++q) part[nodes_[q]] = t.p0;
                 continue;
             }
-            const int kl = t.k / 2;
-            const int n = t.hi - t.lo;
-            const int nl = static_cast<int>(static_cast<long long>(n) * kl / t.k);
-            if (n > 0) {
-                reorder(nodes.data() + t.lo, asc_.data() + t.lo, n);
-                split_ascending(nodes.data() + t.lo, asc_.data() + t.lo, n, nl);
-            }
-            // left half is emitted first: push it last
-            stack.push_back({t.lo + nl, t.hi, t.k - kl});
-            stack.push_back({t.lo, t.lo + nl, kl});
+            BisectTask left, right;
+            split(t, left, right);
+            stack.push_back(right);
+            stack.push_back(left);
         }
     }
 
@@ -169,9 +179,56 @@ class Bisection {
     }
 
     const Graph& g_;
-    std::vector<int> in_, seen_, depth_, asc_, tmp_;
+    int *nodes_, *asc_;
+    std::vector<int> in_, seen_, depth_, tmp_;
     int tag_ = 0, set_ = -1, mark_ = -1;
 };
+
+// Recursive bisection of all V nodes into k parts (see the file comment):
+// the top of the recursion is split level by level, the tasks of a level
+// on threads of their own, until there are enough subtrees for the
+// threads; each subtree is then finished on a thread.
+void bisect(const Graph& g, int k, std::vector<int>& part) {
+    const int V = static_cast<int>(g.off.size()) - 1;
+    std::vector<int> nodes(V), asc(V);
+    std::iota(nodes.begin(), nodes.end(), 0);
+    std::iota(asc.begin(), asc.end(), 0);
+    const int hw = static_cast<int>(std::thread::hardware_concurrency());
+    const int T = std::max(1, std::min(hw, 8));
+    auto run_all = [&](int n_tasks, const auto& work) {
+        if (n_tasks == 1 || T == 1) {
+            for (int i = 0; i < n_tasks; ++i) work(i);
+            return;
+        }
+        std::vector<std::thread> th;
+        th.reserve(n_tasks);
+        for (int i = 0; i < n_tasks; ++i) th.emplace_back(work, i);
+        for (auto& x : th) x.join();
+    };
+    std::vector<BisectTask> level{{0, V, k, 0}};
+    while (static_cast<int>(level.size()) < T) {
+        std::vector<BisectTask> next(2 * level.size());
+        bool any = false;
+        for (const BisectTask& t : level) any |= t.k > 1;
+        if (!any) break;
+        run_all(static_cast<int>(level.size()), [&](int i) {
+            const BisectTask& t = level[i];
+            if (t.k <= 1) {  // a finished part (k = 1) or a placeholder (k = 0) moves down as it is
+                next[2 * i] = t;
+                next[2 * i + 1] = {t.hi, t.hi, 0, t.p0};  // placeholder: nothing to do
+                return;
+            }
+            Bisection b(g, nodes.data(), asc.data());
+            b.split(t, next[2 * i], next[2 * i + 1]);
+        });
+        level.swap(next);
+    }
+    run_all(static_cast<int>(level.size()), [&](int i) {
+        if (level[i].k < 1) return;
+        Bisection b(g, nodes.data(), asc.data());
+        b.finish(level[i], part.data());
+    });
+}
 
 // Components of the units of each domain under the block pattern (rp, ci)
 // over units.  Returns the next-level id of every unit (-1 if empty) and the
@@ -413,7 +470,7 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
     }
     for (int No = 0; No < N && !found; ++No) {
         const int M = (V + (N - No) - 1) / (N - No);
-        Bisection(g).run(M, P.part);
+        bisect(g, M, P.part);
         std::vector<int> size(M, 0);
         bool fits = true;
         for (int i = 0; i < V; ++i) fits &= (++size[P.part[i]] <= N);
