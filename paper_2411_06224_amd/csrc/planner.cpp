@@ -504,18 +504,28 @@ std::string analyze(int V, int nnzb, const int32_t* row_ptr, const int32_t* col_
         P.rp0[s + 1] = P.rp0[s] + (i >= 0 ? row_ptr[i + 1] - row_ptr[i] : 0);
     }
     {
-        std::vector<std::pair<int, int>> row;
-        for (int s = 0; s < P.NS; ++s) {
-            const int i = P.remap[s];
-            if (i < 0) continue;
-            row.clear();
-            for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) row.emplace_back(P.map[col_idx[p]], p);
-            std::sort(row.begin(), row.end());
-            for (size_t q = 0; q < row.size(); ++q) {
-                P.ci0[P.rp0[s] + q] = row[q].first;
-                P.perm_src[P.rp0[s] + q] = row[q].second;
+        // rows are independent: ranges of slots on up to eight threads
+        auto rows = [&](int s0, int s1) {
+            std::vector<std::pair<int, int>> row;
+            for (int s = s0; s < s1; ++s) {
+                const int i = P.remap[s];
+                if (i < 0) continue;
+                row.clear();
+                for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) row.emplace_back(P.map[col_idx[p]], p);
+                std::sort(row.begin(), row.end());
+                for (size_t q = 0; q < row.size(); ++q) {
+                    P.ci0[P.rp0[s] + q] = row[q].first;
+                    P.perm_src[P.rp0[s] + q] = row[q].second;
+                }
             }
-        }
+        };
+        const int T = nnzb >= (1 << 16) ? std::max(1, std::min(static_cast<int>(std::thread::hardware_concurrency()), 8)) : 1;
+        std::vector<std::thread> th;
+        for (int w = 1; w < T; ++w)
+            th.emplace_back(rows, static_cast<int>(static_cast<long long>(P.NS) * w / T),
+                            static_cast<int>(static_cast<long long>(P.NS) * (w + 1) / T));
+        rows(0, static_cast<int>(static_cast<long long>(P.NS) / T));
+        for (auto& x : th) x.join();
     }
 
     // ---- hierarchy
